@@ -1,0 +1,249 @@
+"""CPU oracle for LINE-style edge-sampled SGD -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct reference (``oracle.c``, binary64) that the GPU
+library is checked against.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with the
+GPU library and imports nothing from it.
+
+Every function cites the passage of the paper (NOMAD, arXiv 2604.09419) it follows;
+the C source holds the full statement of each step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+          "-fno-fast-math", "-Wall", "-Wextra"]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (no contraction, no fast-math)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64, u64, u32, i32, f64 = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_int, ctypes.c_double)
+        L.or_philox4x64_10.argtypes = [u64, u64, P, P]
+        L.or_cscan.argtypes = [P, i64, P]
+        L.or_mscan.argtypes = [P, i64, P]
+        L.or_out_degree.argtypes = [P, i64, i64, P]
+        L.or_neg_weights.argtypes = [P, i64, P]
+        L.or_alias_build.argtypes = [P, i64, P, P]
+        L.or_alias_build.restype = i32
+        L.or_sample.argtypes = [i64, i64, P, P, P, P, P, P, u64, u32, i32, u64, u64, P, P, P]
+        L.or_init_table.argtypes = [P, i32, i64, i32, u64, u32]
+        L.or_train.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
+                               f64, f64, f64, u64, P, P, P, u64, u64, i32, u64]
+        L.or_train.restype = i32
+        L.or_train_hogwild_f32.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
+                                           f64, f64, f64, u64, P, P, P, u64, u64, i32]
+        L.or_train_hogwild_f32.restype = i32
+        L.or_max_threads.restype = i32
+        L.or_auc.argtypes = [P, i64, P, i64]
+        L.or_auc.restype = f64
+        L.or_pair_scores.argtypes = [P, P, i32, P, P, i64, P]
+        L.or_draw_item.argtypes = [P, P, i64, u64, u64]
+        L.or_draw_item.restype = i64
+        L.or_apply_tuple.argtypes = [P, P, i32, i32, i32, P, f64, f64, f64]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------------------
+# Counter-based generator: Philox4x64-10 (Salmon et al., SC'11).
+# --------------------------------------------------------------------------
+def philox(key, ctr) -> np.ndarray:
+    """One Philox4x64-10 block for key (2 words) and counter (4 words)."""
+    c = _c(ctr, np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().or_philox4x64_10(int(key[0]), int(key[1]), _p(c), _p(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Canonical FP64 scan and alias tables (encoding of the discrete distributions of
+# Eq. (1) and of Algorithm 3's root-edge selection).
+# --------------------------------------------------------------------------
+def cscan(x) -> np.ndarray:
+    x = _c(x, np.float64)
+    out = np.zeros_like(x)
+    lib().or_cscan(_p(x), x.size, _p(out))
+    return out
+
+
+def mscan(x) -> np.ndarray:
+    x = _c(x, np.float64)
+    out = np.zeros_like(x)
+    lib().or_mscan(_p(x), x.size, _p(out))
+    return out
+
+
+def out_degree(src, n: int) -> np.ndarray:
+    """d(v) of Eq. (1): number of arcs leaving v."""
+    s = _c(src, np.int32)
+    deg = np.zeros(n, dtype=np.int64)
+    lib().or_out_degree(_p(s), s.size, n, _p(deg))
+    return deg
+
+
+def neg_weights(deg) -> np.ndarray:
+    """Eq. (1) numerator d(v)^0.75, as sqrt(d) * sqrt(sqrt(d)) in binary64."""
+    d = _c(deg, np.int64)
+    out = np.zeros(d.size, dtype=np.float64)
+    lib().or_neg_weights(_p(d), d.size, _p(out))
+    return out
+
+
+def alias_build(w):
+    """Alias table (thr uint64[N], alias int32[N]) for weights w (float64)."""
+    w = _c(w, np.float64)
+    thr = np.zeros(w.size, dtype=np.uint64)
+    al = np.zeros(w.size, dtype=np.int32)
+    rc = lib().or_alias_build(_p(w), w.size, _p(thr), _p(al))
+    if rc != 0:
+        raise ValueError("total weight is zero or not finite")
+    return thr, al
+
+
+def draw_item(thr, alias, x0: int, x1: int) -> int:
+    """Item chosen by the words (x0, x1): col = floor(x0 N / 2^64), then the alias test."""
+    thr = _c(thr, np.uint64)
+    alias = _c(alias, np.int32)
+    return int(lib().or_draw_item(_p(thr), _p(alias), thr.size, x0, x1))
+
+
+def apply_tuple(A, B, u: int, ids, eta: float, lam: float = 0.0, alpha: float = 1.0):
+    """Apply one sample (u; v = ids[0]; negatives ids[1:]) to float64 tables A, B in place
+    (Algorithm 1 local updates with LineUpdate, Eqs. (2)-(3)).  A and B may be the same
+    array (first-order proximity)."""
+    ids = _c(ids, np.int32)
+    assert A.dtype == np.float64 and A.flags.c_contiguous
+    assert B.dtype == np.float64 and B.flags.c_contiguous
+    lib().or_apply_tuple(_p(A), _p(B), A.shape[1], ids.size - 1, u, _p(ids), eta, lam, alpha)
+
+
+class Tables:
+    """Edge table over arcs (weights w) and negative table over nodes (Eq. (1))."""
+
+    def __init__(self, n: int, src, dst, w):
+        self.n = int(n)
+        self.src = _c(src, np.int32)
+        self.dst = _c(dst, np.int32)
+        self.w = _c(w, np.float32)
+        self.m = int(self.src.size)
+        self.deg = out_degree(self.src, self.n)
+        self.ethr, self.ealias = alias_build(self.w.astype(np.float64))
+        self.nthr, self.nalias = alias_build(neg_weights(self.deg))
+
+
+def sample(t: Tables, seed: int, graph_id: int, K: int, first: int, count: int):
+    """Sampled tuples (u, v, neg[count, K]) for sample indices [first, first+count)."""
+    u = np.zeros(count, dtype=np.int32)
+    v = np.zeros(count, dtype=np.int32)
+    neg = np.zeros(count * max(K, 1), dtype=np.int32)
+    lib().or_sample(t.n, t.m, _p(t.src), _p(t.dst), _p(t.ethr), _p(t.ealias), _p(t.nthr),
+                    _p(t.nalias), seed, graph_id, K, first, count, _p(u), _p(v), _p(neg))
+    return u, v, neg[: count * K].reshape(count, K)
+
+
+def init_table(t: int, rows: int, d: int, seed: int, graph_id: int) -> np.ndarray:
+    """Initial table t (0 = U, 1 = C, 2 = U1): uniform on [-0.5/d, 0.5/d), float32."""
+    out = np.zeros((rows, d), dtype=np.float32)
+    lib().or_init_table(_p(out), t, rows, d, seed, graph_id)
+    return out
+
+
+class Model:
+    """Embedding tables in binary64 plus the hyper-parameters of Algorithm 1."""
+
+    def __init__(self, tables: Tables, d: int, K: int, orders: int, T: int, seed: int,
+                 graph_id: int = 0, eta0: float = 0.025, lam: float = 0.0, alpha: float = 1.0):
+        self.t, self.d, self.K, self.orders, self.T = tables, d, K, orders, T
+        self.seed, self.graph_id = seed, graph_id
+        self.eta0, self.lam, self.alpha = eta0, lam, alpha
+        n = tables.n
+        self.U = self.C = self.U1 = None
+        if orders & 2:
+            self.U = init_table(0, n, d, seed, graph_id).astype(np.float64)
+            self.C = init_table(1, n, d, seed, graph_id).astype(np.float64)
+        if orders & 1:
+            self.U1 = init_table(2, n, d, seed, graph_id).astype(np.float64)
+
+    def train(self, first: int, count: int, mode: str = "seq", batch: int = 0):
+        """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch)."""
+        t = self.t
+        rc = lib().or_train(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                            _p(t.nthr), _p(t.nalias), self.seed, self.graph_id, self.d, self.K,
+                            self.orders, self.eta0, self.lam, self.alpha, self.T, _p(self.U),
+                            _p(self.C), _p(self.U1), first, count,
+                            0 if mode == "seq" else 1, batch)
+        if rc != 0:
+            raise ValueError("or_train rejected its arguments")
+
+    def scores(self, u, v, order: int) -> np.ndarray:
+        """Link score: U[u].C[v] (order 2) or U1[u].U1[v] (order 1), binary64."""
+        A, B = (self.U, self.C) if order == 2 else (self.U1, self.U1)
+        return pair_scores(A, B, u, v)
+
+
+def pair_scores(A, B, u, v) -> np.ndarray:
+    A = _c(A, np.float64)
+    B = _c(B, np.float64)
+    u = _c(u, np.int32)
+    v = _c(v, np.int32)
+    out = np.zeros(u.size, dtype=np.float64)
+    lib().or_pair_scores(_p(A), _p(B), A.shape[1], _p(u), _p(v), u.size, _p(out))
+    return out
+
+
+def train_hogwild_f32(tables: Tables, U, C, U1, d, K, orders, T, seed, graph_id, first, count,
+                      nthreads, eta0=0.025, lam=0.0, alpha=1.0):
+    """Binary32 lock-free timing mode on ``nthreads`` OpenMP threads (tables updated in place)."""
+    t = tables
+    rc = lib().or_train_hogwild_f32(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                                    _p(t.nthr), _p(t.nalias), seed, graph_id, d, K, orders,
+                                    eta0, lam, alpha, T, _p(U), _p(C), _p(U1), first, count,
+                                    nthreads)
+    if rc != 0:
+        raise ValueError("or_train_hogwild_f32 rejected its arguments")
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
+
+
+def auc(pos, neg) -> float:
+    """Mann-Whitney AUC of positive vs negative scores, ties counted one half."""
+    p = _c(pos, np.float64)
+    q = _c(neg, np.float64)
+    return float(lib().or_auc(_p(p), p.size, _p(q), q.size))

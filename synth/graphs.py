@@ -1,0 +1,199 @@
+"""Seeded synthetic graphs with the shapes of the workloads the method is measured on.
+
+Every array is produced by ``numpy.random.default_rng(seed)`` (PCG64), so a given seed
+gives the same graph on every machine with the same numpy.  The recipe:
+
+* R-MAT (Chakrabarti, Zhan, Faloutsos 2004) with quadrant probabilities
+  (a, b, c, d) = (0.57, 0.19, 0.19, 0.05).  One uniform draw per level picks the
+  quadrant; bit ``l`` of the source is set for quadrants c, d and bit ``l`` of the
+  destination for quadrants b, d.
+* Self-loops and IDs >= n are rejected, duplicates are dropped keeping the first
+  occurrence (generation order), and generation continues until exactly ``m`` unique
+  edges exist.  For an undirected graph the pair is canonicalised to (min, max) for
+  de-duplication and stored as two arcs, (u, v) then (v, u).
+* Vertex IDs are relabelled with a seeded random permutation so that hubs are spread
+  over the tables instead of sitting at low IDs.
+* Weights are 1 (unit) or lognormal(mu=0, sigma=1) rounded to float32, one draw per
+  unique edge (both arcs of an undirected edge share it).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+RMAT_ABC = (0.57, 0.19, 0.19)
+
+
+@dataclass
+class Graph:
+    n: int
+    src: np.ndarray  # int32[m]
+    dst: np.ndarray  # int32[m]
+    w: np.ndarray  # float32[m]
+    directed: bool = True
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+def _rmat_keys(rng, scale: int, n: int, count: int, directed: bool, abc=RMAT_ABC):
+    """Draw ``count`` R-MAT pairs, reject out-of-range IDs and self-loops, return keys."""
+    a, b, c = abc
+    ab, abc_ = a + b, a + b + c
+    u = np.zeros(count, dtype=np.int64)
+    v = np.zeros(count, dtype=np.int64)
+    for lvl in range(scale):
+        r = rng.random(count)
+        sbit = r >= ab
+        dbit = ((r >= a) & (r < ab)) | (r >= abc_)
+        u |= sbit.astype(np.int64) << lvl
+        v |= dbit.astype(np.int64) << lvl
+    keep = (u < n) & (v < n) & (u != v)
+    u, v = u[keep], v[keep]
+    if not directed:
+        lo, hi = np.minimum(u, v), np.maximum(u, v)
+        u, v = lo, hi
+    return u * n + v
+
+
+def rmat_graph(scale: int, n: int, m_unique: int, seed: int, directed: bool = True,
+               weights: str = "lognormal", abc=RMAT_ABC, relabel: bool = True) -> Graph:
+    """R-MAT graph with exactly ``m_unique`` unique edges (see module docstring)."""
+    if n > (1 << scale):
+        raise ValueError("n exceeds 2**scale")
+    rng = np.random.default_rng(seed)
+    keys = np.empty(0, dtype=np.int64)
+    need = m_unique
+    while True:
+        batch = int(need * 1.3) + 4096
+        fresh = _rmat_keys(rng, scale, n, batch, directed, abc)
+        allk = np.concatenate([keys, fresh])
+        _, first = np.unique(allk, return_index=True)
+        first.sort()
+        keys = allk[first]
+        if keys.shape[0] >= m_unique:
+            keys = keys[:m_unique]
+            break
+        need = m_unique - keys.shape[0]
+    u = (keys // n).astype(np.int64)
+    v = (keys % n).astype(np.int64)
+    if relabel:
+        perm = rng.permutation(n).astype(np.int64)
+        u, v = perm[u], perm[v]
+    if weights == "unit":
+        w = np.ones(m_unique, dtype=np.float32)
+    elif weights == "lognormal":
+        w = rng.lognormal(0.0, 1.0, size=m_unique).astype(np.float32)
+    else:
+        raise ValueError(weights)
+    if directed:
+        src, dst, ww = u, v, w
+    else:
+        src = np.empty(2 * m_unique, dtype=np.int64)
+        dst = np.empty(2 * m_unique, dtype=np.int64)
+        src[0::2], dst[0::2] = u, v
+        src[1::2], dst[1::2] = v, u
+        ww = np.repeat(w, 2)
+    return Graph(n=n, src=src.astype(np.int32), dst=dst.astype(np.int32),
+                 w=np.ascontiguousarray(ww, dtype=np.float32), directed=directed,
+                 meta=dict(kind="rmat", scale=scale, seed=seed, m_unique=m_unique))
+
+
+def holdout_split(g: Graph, seed: int, frac_den: int = 100):
+    """Hold out exactly floor(m / frac_den) arcs, chosen by ``seed``.
+
+    Returns (train_graph, held_src, held_dst).  The training graph keeps the
+    remaining arcs in their original order."""
+    rng = np.random.default_rng(seed)
+    k = g.m // frac_den
+    idx = np.sort(rng.choice(g.m, size=k, replace=False))
+    mask = np.ones(g.m, dtype=bool)
+    mask[idx] = False
+    train = Graph(n=g.n, src=g.src[mask].copy(), dst=g.dst[mask].copy(), w=g.w[mask].copy(),
+                  directed=g.directed, meta=dict(g.meta, held_out=k))
+    return train, g.src[idx].copy(), g.dst[idx].copy()
+
+
+def auc_negatives(n: int, all_src: np.ndarray, all_dst: np.ndarray, held_src: np.ndarray,
+                  seed: int) -> np.ndarray:
+    """One negative endpoint per held-out arc (u, v): v' uniform on [0, n) minus {u},
+    redrawn while (u, v') is an arc of the full graph (training plus held-out)."""
+    rng = np.random.default_rng(seed)
+    ekeys = np.sort(all_src.astype(np.int64) * n + all_dst.astype(np.int64))
+    u = held_src.astype(np.int64)
+    out = np.empty(u.shape[0], dtype=np.int64)
+    todo = np.arange(u.shape[0])
+    while todo.size:
+        cand = rng.integers(0, n - 1, size=todo.size)
+        cand = cand + (cand >= u[todo])
+        key = u[todo] * n + cand
+        pos = np.searchsorted(ekeys, key)
+        pos = np.minimum(pos, ekeys.size - 1)
+        bad = ekeys[pos] == key
+        out[todo[~bad]] = cand[~bad]
+        todo = todo[bad]
+    return out.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  C1 is the small correctness case, C2/C3 the headline
+# d=128 case, C4 the batched case and C5 the large single-GPU share.
+# ---------------------------------------------------------------------------
+CONFIGS = {
+    "C1": dict(scale=14, n=10_000, m_unique=100_000, seed=1, directed=False, weights="unit",
+               d=16, K=5, T=1_000_000, eta0=0.025, orders=2, dtype="fp32"),
+    "C2": dict(scale=20, n=1 << 20, m_unique=1 << 24, seed=2, directed=True, weights="lognormal",
+               d=128, K=5, T=200_000_000, eta0=0.025, orders=3, dtype="fp32", holdout=True),
+    "C3": dict(scale=20, n=1 << 20, m_unique=1 << 24, seed=2, directed=True, weights="lognormal",
+               d=128, K=5, T=200_000_000, eta0=0.025, orders=3, dtype="bf16", holdout=True),
+    "C5": dict(scale=26, n=1 << 26, m_unique=1 << 30, seed=5, directed=True, weights="lognormal",
+               d=128, K=5, T=10_000_000_000, eta0=0.025, orders=2, dtype="bf16"),
+}
+
+
+def config_graph(name: str, holdout: Optional[bool] = None):
+    """Training graph of a named workload.
+
+    Returns ``(train, held_src, held_dst, neg_dst)``; the last three are None when the
+    workload has no hold-out.  ``holdout=True`` on C1 gives its 1 % AUC variant."""
+    cfg = CONFIGS[name]
+    g = rmat_graph(cfg["scale"], cfg["n"], cfg["m_unique"], cfg["seed"], cfg["directed"],
+                   cfg["weights"])
+    g.meta["config"] = name
+    if holdout is None:
+        holdout = bool(cfg.get("holdout", False))
+    if not holdout:
+        return g, None, None, None
+    train, hs, hd = holdout_split(g, seed=cfg["seed"] * 1000 + 7)
+    neg = auc_negatives(g.n, g.src, g.dst, hs, seed=cfg["seed"] * 1000 + 11)
+    return train, hs, hd, neg
+
+
+def batch_graph_specs(G: int = 64, base_seed: int = 4000, n_lo: float = 1e3, n_hi: float = 2e6,
+                      deg_lo: float = 8.0, deg_hi: float = 32.0):
+    """Sizes of the batched workload: per graph g, seed base_seed+g draws
+    n_g = round(exp(U(ln n_lo, ln n_hi))), mean out-degree U[deg_lo, deg_hi],
+    m_g = round(n_g * deg), d_g in {64, 128} with probability 1/2, R-MAT scale
+    ceil(log2 n_g)."""
+    specs = []
+    for gi in range(G):
+        rng = np.random.default_rng(base_seed + gi)
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        deg = float(rng.uniform(deg_lo, deg_hi))
+        m = int(round(n * deg))
+        d = int(rng.choice([64, 128]))
+        scale = max(1, int(math.ceil(math.log2(n))))
+        specs.append(dict(g=gi, seed=base_seed + gi, n=n, m=m, d=d, scale=scale, T=20 * m))
+    return specs
+
+
+def batch_graph(spec: dict) -> Graph:
+    """One graph of the batched workload from its spec (directed R-MAT, lognormal)."""
+    g = rmat_graph(spec["scale"], spec["n"], spec["m"], spec["seed"] + 100_000, True, "lognormal")
+    g.meta.update(spec)
+    return g
