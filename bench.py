@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of LINE edge-sampled SGD on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload C2]
+
+One step = the whole hot path over the workload's synthetic graph, arcs already in HBM:
+validate the arcs and count out-degrees, build both alias tables (binary64 normalisation
+and prefix sums), initialise the embedding tables, then train all T edge samples (Philox
+draws, row gathers, dot products, scatter updates) with the Hogwild kernel.  ``value`` is
+T / (mean step time) in edge samples per second.
+
+Default workload (C2): directed R-MAT scale 20 (2^20 nodes, 2^24 unique arcs, 1 % held
+out), lognormal(0, 1) weights, d = 128, K = 5, first + second order, binary32 tables,
+T = 2e8, eta 0.025 decaying linearly to 0.  After the timed steps the same hot path runs
+with bfloat16 tables (C3) for the BF16-over-FP32 speedup, and the held-out AUC of both
+is compared with the binary64 oracle's.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge samples/sec at d=128,K=5 + HBM GB/s; BF16 vs FP32 at equal AUC"
+PEAK_HBM_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def algorithmic_bytes_per_sample(d: int, K: int, orders: int, elem_bytes: int) -> int:
+    """Bytes the method must move per edge sample: per order, (2 + K) rows read and
+    written (vertex row, positive context row, K negative context rows), plus one
+    32-byte edge alias record (threshold, alias, both arcs' endpoints) and K 16-byte
+    negative alias records."""
+    n_orders = bin(orders).count("1")
+    return n_orders * 2 * (2 + K) * d * elem_bytes + 32 + 16 * K
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from synth import CONFIGS, config_graph
+    cfg = dict(CONFIGS[name])
+    t0 = time.time()
+    g, hs, hd, neg = config_graph(name)
+    log(f"[bench] {name}: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
+    return cfg, g, hs, hd, neg
+
+
+def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache):
+    """Time `steps` full passes (after `warmup`); return timings and the trainer."""
+    import torch
+    from paper_2604_09419_amd import Trainer
+    T = int(cfg["T"])
+    tr = Trainer(g.n, g.src, g.dst, g.w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype=dtype,
+                 eta0=cfg["eta0"], seed=seed, total_samples=T, build=False, init=False)
+    # Tuning happens once, outside the timed region, with the step size scaled to zero.
+    tr.build_alias()
+    tr.tune(probe=min(T, 20_000_000), cache_path=tune_cache)
+    step_ms, kern_ms = [], []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        from paper_2604_09419_amd import _lib
+        _lib.lh_set_graph(tr.h, tr.n, tr.m, tr.src.data_ptr(), tr.dst.data_ptr(), tr.w.data_ptr())
+        tr.build_alias()
+        tr.init_embeddings()
+        tr.train_steps(0, T)
+        tr.synchronize()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * 1e3
+        km = tr.last_train_ms()
+        if i >= warmup:
+            step_ms.append(dt)
+            kern_ms.append(km)
+        log(f"[bench] {dtype} step {i} ({'warmup' if i < warmup else 'timed'}): {dt:.1f} ms, "
+            f"train kernel {km:.1f} ms")
+    tr.check()
+    return tr, step_ms, kern_ms
+
+
+def held_out_auc(tr, hs, hd, neg, orders):
+    import numpy as np
+    from paper_2604_09419_amd import LH_TABLE_C, LH_TABLE_U, LH_TABLE_U1
+
+    def dots(A, B, u, v):
+        return np.einsum("ij,ij->i", A[u].astype(np.float64), B[v].astype(np.float64))
+
+    def auc(p, q):
+        from scipy.stats import rankdata
+        r = rankdata(np.concatenate([p, q]))
+        return float((r[: p.size].sum() - p.size * (p.size + 1) / 2) / (p.size * q.size))
+
+    out = {}
+    if orders & 2:
+        U = tr.read(LH_TABLE_U).cpu().numpy()
+        C = tr.read(LH_TABLE_C).cpu().numpy()
+        out["uc"] = auc(dots(U, C, hs, hd), dots(U, C, hs, neg))
+        uu = (dots(U, U, hs, hd), dots(U, U, hs, neg))
+        out["uu"] = auc(*uu)
+    if orders & 1:
+        U1 = tr.read(LH_TABLE_U1).cpu().numpy()
+        o1 = (dots(U1, U1, hs, hd), dots(U1, U1, hs, neg))
+        out["o1"] = auc(*o1)
+    if orders == 3:
+        out["concat"] = auc(uu[0] + o1[0], uu[1] + o1[1])
+    return out
+
+
+def cpu_baseline(cfg, g, seed, target_s=15.0):
+    """The oracle's binary32 Hogwild mode on the host cores, on a bounded prefix of the
+    same sample stream."""
+    import numpy as np
+    import oracle
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.time()
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+    d, K, orders, T = cfg["d"], cfg["K"], cfg["orders"], int(cfg["T"])
+    U = oracle.init_table(0, g.n, d, seed, 0) if orders & 2 else None
+    C = oracle.init_table(1, g.n, d, seed, 0) if orders & 2 else None
+    U1 = oracle.init_table(2, g.n, d, seed, 0) if orders & 1 else None
+    log(f"[bench] oracle tables ready in {time.time() - t0:.1f}s, {threads} threads")
+    probe = 200_000
+    t1 = time.perf_counter()
+    oracle.train_hogwild_f32(tb, U, C, U1, d, K, orders, T, seed, 0, 0, probe, threads)
+    rate = probe / (time.perf_counter() - t1)
+    count = int(min(max(rate * target_s, probe), T - probe))
+    t2 = time.perf_counter()
+    oracle.train_hogwild_f32(tb, U, C, U1, d, K, orders, T, seed, 0, probe, count, threads)
+    dt = time.perf_counter() - t2
+    del U, C, U1
+    return {"value": count / dt, "unit": "edge samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"samples [{probe}, {probe + count}) of the same workload and seed "
+                      f"({count} samples, {dt:.1f} s), binary32 lock-free mode of the oracle, "
+                      f"{threads} OpenMP threads; alias build and init excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=["C2"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
+    ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "_work", "tune_cache.json"))
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+
+    cfg, g, hs, hd, neg = workload(args.workload)
+    seed = cfg["seed"]
+    tr, step_ms, kern_ms = run_gpu_leg(cfg, g, "fp32", args.steps, args.warmup, seed, args.tune_cache)
+    T = int(cfg["T"])
+    ms_step = sum(step_ms) / len(step_ms)
+    ms_kern = sum(kern_ms) / len(kern_ms)
+    bps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 4)
+    achieved = bps * T / (ms_kern * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": T / (ms_step * 1e-3),
+        "unit": "edge samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "C2: directed R-MAT scale 20 (a,b,c=0.57,0.19,0.19), 1048576 nodes, "
+                        f"{g.m} training arcs (1% of 2^24 held out), lognormal(0,1) weights, d=128, K=5, "
+                        "orders 1+2, binary32 tables, T=2e8 edge samples, eta 0.025 linear decay, Hogwild",
+            "n": g.n, "m": g.m, "d": cfg["d"], "K": cfg["K"], "orders": cfg["orders"], "T": T,
+            "kernel_config": tr.kernel_config(),
+        },
+        "train_only": {"samples_per_s": T / (ms_kern * 1e-3), "ms": ms_kern},
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "kernel": "k_hogwild (binary32, orders 1+2)", "bytes_per_sample": bps,
+        },
+    }
+    if not args.no_auc:
+        t0 = time.time()
+        result["auc_fp32"] = held_out_auc(tr, hs, hd, neg, cfg["orders"])
+        log(f"[bench] fp32 AUC {result['auc_fp32']} ({time.time() - t0:.1f}s)")
+    tr.close()
+    del tr
+    torch.cuda.empty_cache()
+
+    if not args.no_bf16:
+        tb, bsteps, bkern = run_gpu_leg(cfg, g, "bf16", max(1, args.steps), 1, seed, args.tune_cache)
+        bms = sum(bkern) / len(bkern)
+        bbps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 2)
+        bach = bbps * T / (bms * 1e-3) / 1e9
+        result["bf16"] = {
+            "samples_per_s": T / (sum(bsteps) / len(bsteps) * 1e-3),
+            "train_only_samples_per_s": T / (bms * 1e-3),
+            "speedup_train_vs_fp32": ms_kern / bms,
+            "speedup_step_vs_fp32": ms_step / (sum(bsteps) / len(bsteps)),
+            "roofline": {"bound": "hbm", "achieved": bach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": bach / PEAK_HBM_GBS, "bytes_per_sample": bbps},
+        }
+        if not args.no_auc:
+            result["bf16"]["auc"] = held_out_auc(tb, hs, hd, neg, cfg["orders"])
+            log(f"[bench] bf16 AUC {result['bf16']['auc']}")
+        tb.close()
+        del tb
+        torch.cuda.empty_cache()
+
+    gold_path = os.path.join(GOLDEN, "c2_oracle_auc.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        result["auc_oracle_binary64"] = {k[4:]: v for k, v in gold.items()
+                                         if k.startswith("auc_") and not k.startswith("auc_init")}
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(cfg, g, seed)
+        log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.3e} samples/s")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * linehip -- LINE-style edge-sampled SGD for graph embeddings on AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * The method (NOMAD, arXiv 2604.09419, Sec. IV "Methods"):
+ *   * a positive pair is an arc (u, v) drawn from the weight-normalised edge
+ *     distribution (Algorithm 3, root-edge selection);
+ *   * K negatives v- are drawn i.i.d. from q(v) proportional to d(v)^0.75, d the
+ *     out-degree (Eq. (1));
+ *   * per pair the signed gradient scalar is g = eta (1 - sigma(U[u].C[v])) for the
+ *     positive and g = -eta alpha_neg sigma(U[u].C[v-]) for a negative (Algorithm 1,
+ *     local updates), and LineUpdate / Eqs. (2)-(3) add g*C[.] - eta*lambda*U[u] to the
+ *     vertex row and g*U0 - eta*lambda*C[.] to the context row;
+ *   * a deterministic mode computes a batch's increments from the tables as they were
+ *     at the batch start and sums them per row before applying (Eq. (4)).
+ * First-order proximity (one table U1 at both ends) uses the same tuples.
+ *
+ * Conventions shared by every call
+ *   - Pointers are plain addresses.  "device" means memory allocated on the handle's
+ *     GPU (hipMalloc, or a torch tensor on that GPU); "host" means ordinary CPU memory.
+ *   - The caller owns every buffer it passes in; the library never frees caller
+ *     memory.  A handle owns only small host metadata and one int64 device status word.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Every call
+ *     enqueues its work on the handle's stream and returns without synchronising,
+ *     except lh_check, lh_export_alias and lh_create/lh_destroy, which synchronise.
+ *   - Argument errors are detected on the host before any GPU work and returned at
+ *     once.  Errors in the data (an ID >= n, a NaN or negative weight, a zero total
+ *     weight) are recorded on the device and reported by lh_check.
+ *   - No call throws; every call returns an lh_status.  A handle must not be used
+ *     from two threads at once; distinct handles are independent.
+ *   - Tables are row-major [n x d] with rows of d elements (d % 8 == 0), binary32 or
+ *     bfloat16 as lh_params.dtype says, and 16-byte-aligned base addresses.
+ */
+#ifndef LINEHIP_H
+#define LINEHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LH_API __attribute__((visibility("default")))
+
+typedef enum {
+    LH_OK = 0,
+    LH_ERR_INVALID_ARG = 1,      /* a null pointer, a size out of range, d % 8 != 0 ... */
+    LH_ERR_OUT_OF_RANGE = 2,     /* device-detected: an arc endpoint >= n              */
+    LH_ERR_ZERO_WEIGHT = 3,      /* device-detected: NaN/negative weight or zero total */
+    LH_ERR_WORKSPACE_TOO_SMALL = 4,
+    LH_ERR_NOT_BUILT = 5,        /* a call needs lh_bind / lh_set_graph / alias first   */
+    LH_ERR_UNSUPPORTED = 6,      /* a parameter combination this build has no kernel for */
+    LH_ERR_NO_DEVICE = 7,        /* no HIP device, or the device index is out of range  */
+    LH_ERR_HIP = 8               /* a HIP runtime call failed; see lh_last_error       */
+} lh_status;
+
+enum { LH_FP32 = 0, LH_BF16 = 1 };
+enum { LH_HOGWILD = 0, LH_SNAPSHOT = 1 };
+enum { LH_ORDER1 = 1, LH_ORDER2 = 2, LH_ORDER12 = 3 };
+enum { LH_TABLE_U = 0, LH_TABLE_C = 1, LH_TABLE_U1 = 2 };
+enum { LH_ALIAS_EDGE = 0, LH_ALIAS_NEG = 1 };
+
+typedef struct {
+    int32_t d;          /* embedding width, d % 8 == 0, 8 <= d <= 512                    */
+    int32_t K;          /* negatives per positive pair, 0 <= K <= 8 (Algorithm 1)        */
+    int32_t orders;     /* LH_ORDER1 | LH_ORDER2 | LH_ORDER12                              */
+    int32_t dtype;      /* LH_FP32 or LH_BF16 (tables; arithmetic is always binary32)     */
+    double eta0;        /* initial step size eta (Sec. V-A: 0.025)                          */
+    double lambda;      /* weight decay lambda of LineUpdate                                */
+    double alpha_neg;   /* negative weight alpha_neg of Algorithm 1                         */
+    uint64_t seed;      /* key word 0 of every Philox4x64-10 block                          */
+    uint64_t total_samples; /* T: eta_s = eta0 (1 - s / T) for global sample index s     */
+    int32_t mode;       /* LH_HOGWILD or LH_SNAPSHOT                                        */
+    int32_t graph_id;   /* low 32 bits of key word 1 (one stream per graph)                 */
+    int64_t batch;      /* SNAPSHOT batch B (samples [bB, (b+1)B) share one snapshot)      */
+} lh_params;
+
+typedef struct lh_handle lh_handle;
+typedef struct lh_batch lh_batch;
+
+/* Create a handle for device `device` after validating *p.  Returns LH_ERR_NO_DEVICE
+ * when no HIP device exists (so it can be probed without a GPU). */
+LH_API lh_status lh_create(lh_handle **h, const lh_params *p, int device);
+
+/* Bytes of device memory the caller must provide for a graph with n nodes and m arcs:
+ * *persist for lh_bind (alias tables, flags, SNAPSHOT buffers) and *scratch for
+ * lh_build_alias (binary64 build arrays, free after that call's work has run).
+ * Host-only; needs no device. */
+LH_API lh_status lh_workspace_size(const lh_params *p, int64_t n, int64_t m, size_t *persist,
+                            size_t *scratch);
+
+/* Attach caller memory.  workspace: device, >= *persist bytes from lh_workspace_size
+ * for the n and m later given to lh_set_graph, 256-byte aligned.  tables[3]: device
+ * pointers to U, C, U1 ([n x d] each, lh_params.dtype), NULL for a table the orders
+ * do not use.  stream: the hipStream_t every later call enqueues on. */
+LH_API lh_status lh_bind(lh_handle *h, void *workspace, size_t bytes, void *const tables[3],
+                  void *stream);
+
+/* The graph: n nodes, m arcs (src[a] -> dst[a], weight w[a]); device arrays that must
+ * stay valid until lh_build_alias's work has run.  An undirected edge is two arcs.
+ * Endpoint and weight checks run on the device (reported by lh_check). */
+LH_API lh_status lh_set_graph(lh_handle *h, int64_t n, int64_t m, const int32_t *src,
+                       const int32_t *dst, const float *w);
+
+/* Build the edge alias table over the m arcs (weights w) and the negative alias table
+ * over the n nodes (weights out-degree^0.75, Eq. (1)) with the binary64 canonical
+ * chunked scan.  scratch: device, >= *scratch bytes from lh_workspace_size. */
+LH_API lh_status lh_build_alias(lh_handle *h, void *scratch, size_t scratch_bytes);
+
+/* Replace (import) or copy out (export) one alias table: which = LH_ALIAS_EDGE (N = m)
+ * or LH_ALIAS_NEG (N = n); thr uint64[N], alias int32[N], both device.  Import
+ * validates nothing beyond sizes; export synchronises the stream. */
+LH_API lh_status lh_import_alias(lh_handle *h, int which, const uint64_t *thr, const int32_t *alias);
+LH_API lh_status lh_export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias);
+
+/* Fill the bound tables with the initial values: uniform on [-0.5/d, 0.5/d), element
+ * (t, r, c) from Philox4x64-10 word c % 4 of key (seed, 2^32 | graph_id), counter
+ * (r, c / 4, t, 0); bfloat16 tables take the round-to-nearest-even of that value. */
+LH_API lh_status lh_init_embeddings(lh_handle *h);
+
+/* Parity hook: the tuples of samples [first, first + count): u[i], v[i] (int32, device,
+ * count each) and neg[i * K + k] (int32, device, count * K).  Sample s slot j uses
+ * Philox4x64-10 key (seed, graph_id), counter (s, j, 0, 0). */
+LH_API lh_status lh_sample(lh_handle *h, uint64_t first, uint64_t count, int32_t *u, int32_t *v,
+                    int32_t *neg);
+
+/* Train samples [first, first + count) in lh_params.mode.  Needs first + count <= T.
+ * SNAPSHOT needs first % batch == 0 and processes batches [bB, min((b+1)B, end)). */
+LH_API lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count);
+
+/* Pick the Hogwild kernel configuration (lanes per sample, 16-byte chunks per lane,
+ * workgroups per compute unit) for this handle's shape by timing each candidate on
+ * samples [0, probe) with the step size scaled to zero, so the tables are left as they
+ * were.  cache_path (may be NULL) names a JSON file of earlier choices keyed by device,
+ * dtype, d, K and orders; a hit skips the timing.  Synchronises. */
+LH_API lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_path);
+
+/* The Hogwild kernel configuration in use: out[0] lanes per sample, out[1] 16-byte chunks
+ * per lane, out[2] workgroups per compute unit (host memory, 3 int32). */
+LH_API lh_status lh_kernel_config(const lh_handle *h, int32_t out[3]);
+
+/* Copy rows [row0, row0 + rows) of table t (LH_TABLE_*) to / from a binary32 device
+ * buffer [rows x d]; bfloat16 tables convert (reads exactly, writes round to nearest even). */
+LH_API lh_status lh_read_embeddings(lh_handle *h, int table, int64_t row0, int64_t rows, float *out);
+LH_API lh_status lh_write_embeddings(lh_handle *h, int table, int64_t row0, int64_t rows,
+                              const float *in);
+
+/* Synchronise the stream and report device-side data errors (LH_ERR_OUT_OF_RANGE,
+ * LH_ERR_ZERO_WEIGHT) recorded since the last lh_check, clearing them. */
+LH_API lh_status lh_check(lh_handle *h);
+
+/* Kernel time of the last lh_train_steps call, in milliseconds, measured with HIP
+ * events on the handle's stream (synchronises).  Returns 0 when nothing was timed. */
+LH_API lh_status lh_last_train_ms(lh_handle *h, double *ms);
+
+LH_API const char *lh_status_string(lh_status s);
+LH_API const char *lh_last_error(const lh_handle *h);
+LH_API lh_status lh_destroy(lh_handle *h);
+
+/* ---------------- Batched: many graphs in one persistent launch ----------------
+ * G handles (HOGWILD, second order, created and bound as above, alias tables built,
+ * tables initialised) are trained together: one persistent kernel pulls (graph, chunk of
+ * samples) items from a device work queue until every graph's [0, T_g) is done.
+ * lh_batch_capture records the queue reset and the kernel into a hipGraph on the first
+ * handle's stream; lh_batch_launch replays it.  lh_batch_tune times the kernel variants
+ * (lanes per sample, samples per item, grid size) on this batch and keeps the fastest;
+ * cache_path (may be NULL) names a JSON file of earlier choices keyed by device and shape.
+ * The batch object owns two small device buffers (the graph descriptors and the work
+ * counters) and the hipGraph; lh_batch_destroy frees them.  It supports second-order
+ * HOGWILD handles of one dtype with rows of at most 16 (bfloat16) or 32 (binary32)
+ * 16-byte chunks; other mixes return LH_ERR_UNSUPPORTED. */
+LH_API lh_status lh_batch_create(lh_batch **b, int G, lh_handle *const *graphs);
+LH_API lh_status lh_batch_tune(lh_batch *b, const char *cache_path);
+LH_API lh_status lh_batch_capture(lh_batch *b);
+LH_API lh_status lh_batch_launch(lh_batch *b);
+LH_API lh_status lh_batch_run(lh_batch *b);   /* same work as launch, without a graph */
+LH_API lh_status lh_batch_last_ms(lh_batch *b, double *ms);
+/* Samples trained per graph by the last launch/run (uint64[G], host; synchronises). */
+LH_API lh_status lh_batch_done(lh_batch *b, uint64_t *done_per_graph);
+LH_API lh_status lh_batch_destroy(lh_batch *b);
+
+/* Number of exported entry points (for load checks) and their names. */
+LH_API int lh_abi_symbol_count(void);
+LH_API const char *lh_abi_symbol_name(int i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINEHIP_H */

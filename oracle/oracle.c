@@ -7,7 +7,7 @@
  * constant generator with the GPU library, and it includes nothing from it.
  *
  * Paper: "NOMAD: Generating Embeddings for Massive Distributed Graphs" (arXiv 2604.09419).
- *   - Eq. (1), Sec. III-A (Distributed Training): negatives follow q(v) ~ d(v)^0.75 with
+ *   - Eq. (1), Sec. IV-A (Distributed Training): negatives follow q(v) ~ d(v)^0.75 with
  *     d(v) the out-degree.
  *   - Algorithm 1 (local updates) and Eqs. (2)-(3): per positive pair
  *     g = eta (1 - sigma(U[u].C[v])); per negative g = -eta alpha_neg sigma(U[u].C[v-]);
@@ -17,7 +17,7 @@
  *     against the copy fetched at the start of the batch (the SNAPSHOT mode below).
  *   - Algorithm 3 (GeneratePairs), root selection: a positive pair is an edge drawn from
  *     the weight-normalised edge distribution.
- *   - Sec. IV-A (Hyperparameters): single-precision SGD, eta = 0.025.
+ *   - Sec. V-A (NOMAD hyperparameters): single-precision SGD, eta = 0.025.
  *
  * Floating point: everything here is IEEE binary64 except the Hogwild timing mode,
  * which is binary32.  Build with -ffp-contract=off and without -ffast-math.

@@ -1,0 +1,371 @@
+// Graph validation and alias-table construction (binary64, built with -ffp-contract=off).
+//
+// The two discrete distributions of the method are encoded as alias tables (Walker
+// 1977 / Vose 1991): the edge distribution of Algorithm 3's root-edge selection
+// (weights w over arcs) and the negative distribution of Eq. (1) (weights
+// out-degree^0.75 over nodes).  The construction is the closed form of the sweeping
+// construction (Huebschle-Schneider and Sanders, "Parallel Weighted Random Sampling"):
+//   W = last element of the canonical scan of w; q_i = fl(fl(w_i N) / W)
+//   lights L = {q < 1}, heavies H = {q >= 1}, each in index order
+//   D = monotone canonical scan of (1 - q) over L, X = the same of (q - 1) over H
+//   light a (start S_a = D[a-1], S_0 = 0): prob q, alias H[min(#{X[k] <= S_a}, |H|-1)]
+//   heavy k < |H|-1: j = #{S_a < X[k]} - 1, overflow o = D[j] - X[k] (0 when j < 0,
+//   clamped at 0); o > 0 gives prob max(0, 1 - o), alias H[k+1]; else prob 1, self
+//   last heavy, or every item when H is empty: prob 1, self
+//   thr = prob >= 1 ? 2^64 - 1 : (uint64)(prob 2^64)
+// Every step is a single correctly rounded binary64 operation in a fixed order, so
+// the tables are bitwise reproducible.
+#include <vector>
+
+#include "handle.hpp"
+#include "scan.hpp"
+
+#pragma clang fp contract(off)
+
+namespace lh {
+
+// ---------------------------------------------------------------------------
+// Validation of the arcs: endpoints in [0, n), weights finite and >= 0.
+// ---------------------------------------------------------------------------
+__global__ void k_validate(const int32_t *src, const int32_t *dst, const float *w, long long m,
+                           long long n, unsigned int *status)
+{
+    long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    int32_t s = src[a], t = dst[a];
+    float x = w[a];
+    unsigned int f = 0;
+    if (s < 0 || (long long)s >= n || t < 0 || (long long)t >= n) f |= ST_OUT_OF_RANGE;
+    if (!(x >= 0.0f) || isinf(x)) f |= ST_BAD_WEIGHT;
+    if (f) atomicOr(status, f);
+}
+
+__global__ void k_clear_status(unsigned int *status) { status[0] = 0u; }
+
+lh_status validate_graph(lh_handle *h)
+{
+    hipStream_t s = h->stream;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, h->status);
+    if (h->m > 0)
+        hipLaunchKernelGGL(k_validate, dim3((unsigned)LH_CDIV(h->m, 256)), dim3(256), 0, s, h->src,
+                           h->dst, h->w, h->m, h->n, h->status);
+    unsigned int st = 0;
+    hipError_t e = hipMemcpyAsync(&st, h->status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "graph validation");
+    if (st & ST_OUT_OF_RANGE) return fail(h, LH_ERR_OUT_OF_RANGE, "an arc endpoint is outside [0, n)");
+    if (st & ST_BAD_WEIGHT) return fail(h, LH_ERR_ZERO_WEIGHT, "a weight is negative, NaN or infinite");
+    return LH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Weights of the two tables, binary64.
+// ---------------------------------------------------------------------------
+__global__ void k_out_degree(const int32_t *src, long long m, int32_t *deg)
+{
+    long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    atomicAdd(&deg[src[a]], 1);
+}
+
+__global__ void k_zero_i32(int32_t *p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_edge_weights(const float *w, long long m, double *wq)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) wq[i] = (double)w[i];
+}
+
+// Eq. (1) numerator: d^0.75 = sqrt(d) * sqrt(sqrt(d)), each step correctly rounded.
+__global__ void k_neg_weights(const int32_t *deg, long long n, double *wq)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = __dsqrt_rn((double)deg[i]);
+    double t = __dsqrt_rn(s);
+    wq[i] = __dmul_rn(s, t);
+}
+
+// q_i = fl(fl(w_i N) / W) in place; light flag (q < 1) into lpos.  A total that is not a
+// positive finite number flags ST_ZERO_TOTAL and makes every item heavy (prob 1, self).
+__global__ void k_normalise(double *wq, const double *scan, long long N, int32_t *lpos,
+                            unsigned int *status)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double W = scan[N - 1];
+    bool ok = W > 0.0 && !isinf(W);
+    double q = ok ? __ddiv_rn(__dmul_rn(wq[i], (double)N), W) : 1.0;
+    if (!ok && i == 0) atomicOr(status, ST_ZERO_TOTAL);
+    wq[i] = q;
+    lpos[i] = q < 1.0 ? 1 : 0;
+}
+
+// Split into lights (prefix of dx/idx) and heavies (suffix), each in index order.
+__global__ void k_split(const double *q, const int32_t *lincl, long long N, long long nL, double *dx,
+                        int32_t *idx)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double qi = q[i];
+    long long inc = lincl[i];
+    if (qi < 1.0) {
+        long long a = inc - 1;
+        dx[a] = __dsub_rn(1.0, qi);
+        idx[a] = (int32_t)i;
+    } else {
+        long long k = i - inc;
+        dx[nL + k] = __dsub_rn(qi, 1.0);
+        idx[nL + k] = (int32_t)i;
+    }
+}
+
+__device__ __forceinline__ unsigned long long prob_to_thr(double prob)
+{
+    if (prob >= 1.0) return ~0ull;
+    return (unsigned long long)__dmul_rn(prob, 18446744073709551616.0);
+}
+
+// #{k : X[k] <= s}
+__device__ __forceinline__ long long count_le(const double *X, long long nH, double s)
+{
+    long long lo = 0, hi = nH;
+    while (lo < hi) {
+        long long mid = lo + (hi - lo) / 2;
+        if (X[mid] <= s)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// #{a : S_a < x} with S_0 = 0 and S_a = D[a-1]
+__device__ __forceinline__ long long count_start_lt(const double *D, long long nL, double x)
+{
+    if (nL == 0 || !(0.0 < x)) return 0;
+    long long lo = 0, hi = nL - 1;
+    while (lo < hi) {
+        long long mid = lo + (hi - lo) / 2;
+        if (D[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return 1 + lo;
+}
+
+struct RecOut {
+    EdgeRec *erec;  // edge table, or
+    NegRec *nrec;   // negative table
+    const int32_t *src, *dst;
+};
+
+__device__ __forceinline__ void write_rec(const RecOut &o, long long i, unsigned long long thr,
+                                          int32_t al)
+{
+    if (o.erec) {
+        EdgeRec r;
+        r.thr = thr;
+        r.alias = al;
+        r.src_c = o.src[i];
+        r.dst_c = o.dst[i];
+        r.src_a = o.src[al];
+        r.dst_a = o.dst[al];
+        r.pad = 0;
+        o.erec[i] = r;
+    } else {
+        NegRec r;
+        r.thr = thr;
+        r.alias = al;
+        r.pad = 0;
+        o.nrec[i] = r;
+    }
+}
+
+__global__ void k_lights(const double *q, const double *dx, const int32_t *idx, long long nL,
+                         long long nH, RecOut o)
+{
+    long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nL) return;
+    long long i = idx[a];
+    if (nH == 0) {
+        write_rec(o, i, ~0ull, (int32_t)i);
+        return;
+    }
+    const double *D = dx, *X = dx + nL;
+    double S = a == 0 ? 0.0 : D[a - 1];
+    long long k = count_le(X, nH, S);
+    if (k > nH - 1) k = nH - 1;
+    write_rec(o, i, prob_to_thr(q[i]), idx[nL + k]);
+}
+
+__global__ void k_heavies(const double *dx, const int32_t *idx, long long nL, long long nH, RecOut o)
+{
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nH) return;
+    const double *D = dx, *X = dx + nL;
+    long long i = idx[nL + k];
+    if (k == nH - 1) {
+        write_rec(o, i, ~0ull, (int32_t)i);
+        return;
+    }
+    long long j = count_start_lt(D, nL, X[k]) - 1;
+    double ov = 0.0;
+    if (j >= 0) {
+        ov = __dsub_rn(D[j], X[k]);
+        if (ov < 0.0) ov = 0.0;
+    }
+    if (ov > 0.0) {
+        double p = __dsub_rn(1.0, ov);
+        write_rec(o, i, prob_to_thr(p < 0.0 ? 0.0 : p), idx[nL + k + 1]);
+    } else {
+        write_rec(o, i, ~0ull, (int32_t)i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver: one table.
+// ---------------------------------------------------------------------------
+static lh_status build_one(lh_handle *h, int which, const ScratchLayout &L, char *sc)
+{
+    hipStream_t s = h->stream;
+    long long N = which == LH_ALIAS_EDGE ? h->m : h->n;
+    double *wq = (double *)(sc + L.wq);
+    double *dx = (double *)(sc + L.dx);
+    int32_t *idx = (int32_t *)(sc + L.idx);
+    int32_t *lpos = (int32_t *)(sc + L.lpos);
+    int32_t *deg = (int32_t *)(sc + L.deg);
+    double *lev = (double *)(sc + L.lev);
+    int32_t *ilev = (int32_t *)(sc + L.ilev);
+    dim3 blk(256), grd((unsigned)LH_CDIV(N, 256));
+
+    if (which == LH_ALIAS_EDGE) {
+        hipLaunchKernelGGL(k_edge_weights, grd, blk, 0, s, h->w, N, wq);
+    } else {
+        hipLaunchKernelGGL(k_zero_i32, grd, blk, 0, s, deg, N);
+        if (h->m > 0)
+            hipLaunchKernelGGL(k_out_degree, dim3((unsigned)LH_CDIV(h->m, 256)), blk, 0, s, h->src, h->m,
+                               deg);
+        hipLaunchKernelGGL(k_neg_weights, grd, blk, 0, s, deg, N, wq);
+    }
+    chunk_scan<OpNeumaier>(wq, dx, N, lev, s);
+    hipLaunchKernelGGL(k_normalise, grd, blk, 0, s, wq, dx, N, lpos, h->status);
+    chunk_scan<OpAdd<int32_t>>(lpos, lpos, N, ilev, s);
+
+    int32_t nL32 = 0;
+    unsigned int st = 0;
+    hipError_t e = hipMemcpyAsync(&nL32, lpos + (N - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&st, h->status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "alias build");
+    if (st & ST_ZERO_TOTAL)
+        return fail(h, LH_ERR_ZERO_WEIGHT,
+                    which == LH_ALIAS_EDGE ? "total arc weight is zero" : "every node has out-degree 0");
+    long long nL = nL32, nH = N - nL;
+
+    hipLaunchKernelGGL(k_split, grd, blk, 0, s, wq, lpos, N, nL, dx, idx);
+    if (nL > 0) {
+        chunk_scan<OpNeumaier>(dx, dx, nL, lev, s);
+        chunk_scan<OpMax>(dx, dx, nL, lev, s);
+    }
+    if (nH > 0) {
+        chunk_scan<OpNeumaier>(dx + nL, dx + nL, nH, lev, s);
+        chunk_scan<OpMax>(dx + nL, dx + nL, nH, lev, s);
+    }
+    RecOut o{which == LH_ALIAS_EDGE ? h->erec : nullptr, which == LH_ALIAS_EDGE ? nullptr : h->nrec,
+             h->src, h->dst};
+    if (nL > 0)
+        hipLaunchKernelGGL(k_lights, dim3((unsigned)LH_CDIV(nL, 256)), blk, 0, s, wq, dx, idx, nL, nH, o);
+    if (nH > 0)
+        hipLaunchKernelGGL(k_heavies, dim3((unsigned)LH_CDIV(nH, 256)), blk, 0, s, dx, idx, nL, nH, o);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "alias kernels");
+    return LH_OK;
+}
+
+lh_status build_alias(lh_handle *h, void *scratch, size_t bytes)
+{
+    ScratchLayout L = scratch_layout(h->n, h->m);
+    if (!scratch) return fail(h, LH_ERR_INVALID_ARG, "scratch is NULL");
+    if (bytes < L.total) return fail(h, LH_ERR_WORKSPACE_TOO_SMALL, "alias scratch too small");
+    h->edge_ready = h->neg_ready = false;
+    lh_status st = build_one(h, LH_ALIAS_EDGE, L, (char *)scratch);
+    if (st != LH_OK) return st;
+    h->edge_ready = true;
+    st = build_one(h, LH_ALIAS_NEG, L, (char *)scratch);
+    if (st != LH_OK) return st;
+    h->neg_ready = true;
+    // The scratch may be released by the caller once this work has run.
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "alias build");
+    return LH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Import / export of (thr, alias) arrays.  Imported alias entries outside [0, N)
+// are replaced by the column itself and flagged, so no later kernel reads out of
+// bounds.
+// ---------------------------------------------------------------------------
+__global__ void k_import(const unsigned long long *thr, const int32_t *alias, long long N, RecOut o,
+                         unsigned int *status)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t al = alias[i];
+    if (al < 0 || (long long)al >= N) {
+        atomicOr(status, ST_OUT_OF_RANGE);
+        al = (int32_t)i;
+    }
+    write_rec(o, i, thr[i], al);
+}
+
+__global__ void k_export(const EdgeRec *erec, const NegRec *nrec, long long N, unsigned long long *thr,
+                         int32_t *alias)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (erec) {
+        thr[i] = erec[i].thr;
+        alias[i] = erec[i].alias;
+    } else {
+        thr[i] = nrec[i].thr;
+        alias[i] = nrec[i].alias;
+    }
+}
+
+lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32_t *alias)
+{
+    long long N = which == LH_ALIAS_EDGE ? h->m : h->n;
+    RecOut o{which == LH_ALIAS_EDGE ? h->erec : nullptr, which == LH_ALIAS_EDGE ? nullptr : h->nrec,
+             h->src, h->dst};
+    if (N > 0)
+        hipLaunchKernelGGL(k_import, dim3((unsigned)LH_CDIV(N, 256)), dim3(256), 0, h->stream,
+                           (const unsigned long long *)thr, alias, N, o, h->status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "alias import");
+    if (which == LH_ALIAS_EDGE)
+        h->edge_ready = true;
+    else
+        h->neg_ready = true;
+    return LH_OK;
+}
+
+lh_status export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias)
+{
+    long long N = which == LH_ALIAS_EDGE ? h->m : h->n;
+    if (N > 0)
+        hipLaunchKernelGGL(k_export, dim3((unsigned)LH_CDIV(N, 256)), dim3(256), 0, h->stream,
+                           which == LH_ALIAS_EDGE ? h->erec : nullptr,
+                           which == LH_ALIAS_EDGE ? nullptr : h->nrec, N,
+                           (unsigned long long *)thr, alias);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "alias export");
+    return LH_OK;
+}
+
+}  // namespace lh

@@ -1,0 +1,511 @@
+// Autotuning of the Hogwild kernel, and many graphs trained in one persistent launch.
+//
+// Batched training: every graph's sample range [0, T_g) is cut into items of S samples.
+// One persistent kernel is launched with a fixed grid; each wavefront takes the next
+// item from a device counter, finds its graph by binary search over the items' prefix
+// offsets, trains the item's 64-sample tiles with the per-sample body used by the
+// single-graph kernel (a width-specific tile configuration chosen inside the kernel), and
+// takes another item until none is left, so every wave reaches the exit.  A counter per
+// graph records how many samples were trained.  The reset of the counters (a kernel, not
+// a memset) and the persistent kernel are captured into one hipGraph.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "handle.hpp"
+#include "tile.hpp"
+
+namespace lh {
+
+// ---------------------------------------------------------------------------
+// Tuning cache: a flat JSON object {"key": [lps, cpl, blocks_per_cu, extra], ...}.
+// ---------------------------------------------------------------------------
+static bool cache_lookup(const char *path, const std::string &key, int out[4])
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string s = ss.str();
+    std::string pat = "\"" + key + "\": [";
+    size_t at = s.find(pat);
+    if (at == std::string::npos) return false;
+    return std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d", &out[0], &out[1], &out[2], &out[3]) == 4;
+}
+
+static void cache_store(const char *path, const std::string &key, const int v[4])
+{
+    if (!path) return;
+    std::string s;
+    {
+        std::ifstream f(path);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            s = ss.str();
+        }
+    }
+    std::vector<std::string> lines;
+    size_t pos = 0;
+    while (true) {  // keep existing entries other than this key
+        size_t q0 = s.find('"', pos);
+        if (q0 == std::string::npos) break;
+        size_t q1 = s.find('"', q0 + 1);
+        size_t b1 = s.find(']', q1);
+        if (q1 == std::string::npos || b1 == std::string::npos) break;
+        std::string k = s.substr(q0 + 1, q1 - q0 - 1);
+        if (k != key) lines.push_back(s.substr(q0, b1 - q0 + 1));
+        pos = b1 + 1;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "\"%s\": [%d, %d, %d, %d]", key.c_str(), v[0], v[1], v[2], v[3]);
+    lines.push_back(buf);
+    std::ofstream o(path);
+    o << "{\n";
+    for (size_t i = 0; i < lines.size(); ++i) o << "  " << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+    o << "}\n";
+}
+
+static std::string arch_name(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static int log2_bucket(long long x)
+{
+    int b = 0;
+    while ((1ll << (b + 1)) <= x) ++b;
+    return b;
+}
+
+}  // namespace lh
+
+using namespace lh;
+
+extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_path)
+{
+    if (!h) return LH_ERR_INVALID_ARG;
+    if (!h->bound || !h->graph_set || !h->edge_ready || !h->neg_ready)
+        return fail(h, LH_ERR_NOT_BUILT, "alias tables not built");
+    if (h->p.mode != LH_HOGWILD) return LH_OK;
+    if (probe < 64 || probe > h->p.total_samples) return fail(h, LH_ERR_INVALID_ARG, "probe out of range");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != h->device) (void)hipSetDevice(h->device);
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s|hogwild|dt%d|d%d|K%d|o%d|n%d", arch_name(h->device).c_str(), h->p.dtype,
+                  h->p.d, h->p.K, h->p.orders, log2_bucket(h->n));
+    int hit[4];
+    if (cache_lookup(cache_path, key, hit)) {
+        TileCfg c;
+        c.lps = hit[0];
+        c.cpl = hit[1];
+        c.blocks_per_cu = hit[2];
+        if (cfg_supported(h->p.dtype, h->p.d, c)) {
+            h->cfg = c;
+            return LH_OK;
+        }
+    }
+    const int vec = h->p.dtype == LH_FP32 ? 4 : 8;
+    const int nch = h->p.d / vec;
+    GraphDev g = graph_dev(h);
+    g.eta_scale = 0.0f;  // dry run: every row is written back unchanged
+    const int lps_opts[] = {2, 4, 8, 16, 32, 64};
+    const int bpc_opts[] = {2, 4, 8, 16};
+    TileCfg best = h->cfg;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LH_ERR_HIP;
+    for (int cpl = 1; cpl <= 2; ++cpl) {
+        for (int lps : lps_opts) {
+            TileCfg c;
+            c.lps = lps;
+            c.cpl = cpl;
+            if (lps * cpl < nch || (lps * cpl >= 2 * nch && lps > 2)) continue;
+            for (int bpc : bpc_opts) {
+                c.blocks_per_cu = bpc;
+                if (!cfg_supported(h->p.dtype, h->p.d, c)) continue;
+                // warm-up, then timed
+                hipError_t er = launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe / 4, h->num_cu, h->status,
+                                               h->stream);
+                if (er != hipSuccess) continue;
+                (void)hipEventRecord(e0, h->stream);
+                (void)launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe, h->num_cu, h->status, h->stream);
+                (void)hipEventRecord(e1, h->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) continue;
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->cfg = best;
+    int v[4] = {best.lps, best.cpl, best.blocks_per_cu, 0};
+    cache_store(cache_path, key, v);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LH_OK : hip_fail(h, e, "tune");
+}
+
+// ===========================================================================
+// Batched persistent training.
+// ===========================================================================
+namespace lh {
+
+struct BatchDesc {
+    GraphDev g;
+    unsigned long long item0;  // index of this graph's first item
+    unsigned long long limit;  // samples to train: [0, limit)
+};
+
+struct BatchArgs {
+    const BatchDesc *desc;
+    int G;
+    unsigned long long total_items;
+    unsigned long long item_samples;
+    unsigned long long *queue;
+    unsigned long long *done;  // [G]
+};
+
+// Tile configurations by variant: 0 = natural lanes per sample, 1 = half the lanes with
+// two chunks each.  SMALL serves rows of at most NCH_SMALL chunks, LARGE the rest.
+template <typename TT, int V>
+struct BatchCfg;
+template <>
+struct BatchCfg<uint16_t, 0> {
+    static constexpr int LS = 8, CS = 1, LL = 16, CL = 1;
+};
+template <>
+struct BatchCfg<uint16_t, 1> {
+    static constexpr int LS = 4, CS = 2, LL = 8, CL = 2;
+};
+template <>
+struct BatchCfg<float, 0> {
+    static constexpr int LS = 16, CS = 1, LL = 32, CL = 1;
+};
+template <>
+struct BatchCfg<float, 1> {
+    static constexpr int LS = 8, CS = 2, LL = 16, CL = 2;
+};
+
+__global__ void k_batch_reset(unsigned long long *queue, unsigned long long *done, int G)
+{
+    int i = threadIdx.x;
+    if (i == 0) queue[0] = 0ull;
+    for (int g = i; g < G; g += blockDim.x) done[g] = 0ull;
+}
+
+template <typename TT, int KMAX, int V>
+__global__ void __launch_bounds__(256) k_batch(BatchArgs a)
+{
+    using Cfg = BatchCfg<TT, V>;
+    const int lane = threadIdx.x & 63;
+    SnapOut so{};
+    while (true) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(a.queue, 1ull);
+        item = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(item >> 32)) << 32) |
+               (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(item & 0xffffffffull));
+        if (item >= a.total_items) break;
+        int lo = 0, hi = a.G - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (a.desc[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchDesc &D = a.desc[lo];
+        const GraphDev g = D.g;
+        unsigned long long s0 = (item - D.item0) * a.item_samples;
+        unsigned long long s1 = s0 + a.item_samples;
+        if (s1 > D.limit) s1 = D.limit;
+        if (g.nch <= Cfg::LS * Cfg::CS) {
+            for (unsigned long long t = s0; t < s1; t += 64)
+                sgd_tile<TT, Cfg::LS, Cfg::CS, KMAX, 2, false>(g, t, s1, so);
+        } else {
+            for (unsigned long long t = s0; t < s1; t += 64)
+                sgd_tile<TT, Cfg::LL, Cfg::CL, KMAX, 2, false>(g, t, s1, so);
+        }
+        if (lane == 0 && s1 > s0) atomicAdd(&a.done[lo], s1 - s0);
+    }
+}
+
+}  // namespace lh
+
+struct lh_batch {
+    std::vector<lh_handle *> hs;
+    int G = 0;
+    int dtype = 0, K = 0, device = 0, num_cu = 256;
+    hipStream_t stream = nullptr;
+    lh::BatchDesc *d_desc = nullptr;        // device, owned
+    unsigned long long *d_ctr = nullptr;    // device, owned: [0] queue, [1..G] done
+    std::vector<lh::BatchDesc> desc;
+    int variant = 0, blocks_per_cu = 8;
+    unsigned long long item_samples = 8192;
+    unsigned long long total_items = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+namespace lh {
+
+static void batch_items(lh_batch *b, unsigned long long item_samples, bool dry, unsigned long long probe)
+{
+    unsigned long long acc = 0;
+    for (int i = 0; i < b->G; ++i) {
+        BatchDesc &D = b->desc[i];
+        D.g = graph_dev(b->hs[i]);
+        D.g.eta_scale = dry ? 0.0f : 1.0f;
+        D.limit = dry ? (probe < D.g.T ? probe : D.g.T) : D.g.T;
+        D.item0 = acc;
+        acc += (D.limit + item_samples - 1) / item_samples;
+    }
+    b->total_items = acc;
+}
+
+static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned long long item_samples)
+{
+    BatchArgs a;
+    a.desc = b->d_desc;
+    a.G = b->G;
+    a.total_items = b->total_items;
+    a.item_samples = item_samples;
+    a.queue = b->d_ctr;
+    a.done = b->d_ctr + 1;
+    hipStream_t s = b->stream;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a.queue, a.done, b->G);
+    dim3 grid((unsigned)(b->num_cu * bpc)), block(256);
+    const bool k5 = b->K <= 5;
+#define LH_BL(TT, KM, V) hipLaunchKernelGGL((k_batch<TT, KM, V>), grid, block, 0, s, a)
+    if (b->dtype == LH_BF16) {
+        if (k5) {
+            if (variant == 0) LH_BL(uint16_t, 5, 0); else LH_BL(uint16_t, 5, 1);
+        } else {
+            if (variant == 0) LH_BL(uint16_t, 8, 0); else LH_BL(uint16_t, 8, 1);
+        }
+    } else {
+        if (k5) {
+            if (variant == 0) LH_BL(float, 5, 0); else LH_BL(float, 5, 1);
+        } else {
+            if (variant == 0) LH_BL(float, 8, 0); else LH_BL(float, 8, 1);
+        }
+    }
+#undef LH_BL
+    return hipGetLastError();
+}
+
+static hipError_t upload_desc(lh_batch *b)
+{
+    return hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(BatchDesc) * b->desc.size(), hipMemcpyHostToDevice,
+                          b->stream);
+}
+
+static void drop_graph(lh_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace lh
+
+extern "C" {
+
+lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
+{
+    if (!out) return LH_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (G < 1 || !graphs) return LH_ERR_INVALID_ARG;
+    for (int i = 0; i < G; ++i) {
+        lh_handle *h = graphs[i];
+        if (!h) return LH_ERR_INVALID_ARG;
+        if (!h->bound || !h->graph_set || !h->edge_ready || !h->neg_ready) return LH_ERR_NOT_BUILT;
+        if (h->p.mode != LH_HOGWILD || h->p.orders != LH_ORDER2) return LH_ERR_UNSUPPORTED;
+        if (h->p.dtype != graphs[0]->p.dtype || h->device != graphs[0]->device) return LH_ERR_UNSUPPORTED;
+        if ((h->p.K <= 5) != (graphs[0]->p.K <= 5)) return LH_ERR_UNSUPPORTED;
+        const int vec = h->p.dtype == LH_FP32 ? 4 : 8;
+        const int nch = h->p.d / vec;
+        const int cap = h->p.dtype == LH_FP32 ? 32 : 16;
+        if (nch > cap) return LH_ERR_UNSUPPORTED;
+    }
+    lh_batch *b = new (std::nothrow) lh_batch();
+    if (!b) return LH_ERR_HIP;
+    b->hs.assign(graphs, graphs + G);
+    b->G = G;
+    b->dtype = graphs[0]->p.dtype;
+    int kmax = 0;
+    for (int i = 0; i < G; ++i) kmax = graphs[i]->p.K > kmax ? graphs[i]->p.K : kmax;
+    b->K = kmax;
+    b->device = graphs[0]->device;
+    b->num_cu = graphs[0]->num_cu;
+    b->stream = graphs[0]->stream;
+    b->desc.resize(G);
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != b->device) (void)hipSetDevice(b->device);
+    if (hipMalloc(&b->d_desc, sizeof(BatchDesc) * G) != hipSuccess ||
+        hipMalloc(&b->d_ctr, sizeof(unsigned long long) * (G + 1)) != hipSuccess ||
+        hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+        lh_batch_destroy(b);
+        return LH_ERR_HIP;
+    }
+    batch_items(b, b->item_samples, false, 0);
+    if (upload_desc(b) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) {
+        lh_batch_destroy(b);
+        return LH_ERR_HIP;
+    }
+    *out = b;
+    return LH_OK;
+}
+
+lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
+{
+    if (!b) return LH_ERR_INVALID_ARG;
+    char key[160];
+    unsigned long long tot = 0;
+    for (auto *h : b->hs) tot += h->p.total_samples;
+    std::snprintf(key, sizeof(key), "%s|batch|dt%d|K%d|G%d|T%d", arch_name(b->device).c_str(), b->dtype, b->K, b->G,
+                  log2_bucket((long long)tot));
+    int hit[4];
+    if (cache_lookup(cache_path, key, hit) && (hit[0] == 0 || hit[0] == 1) && hit[1] >= 1 && hit[1] <= 64 &&
+        hit[2] >= 64) {
+        b->variant = hit[0];
+        b->blocks_per_cu = hit[1];
+        b->item_samples = (unsigned long long)hit[2];
+        drop_graph(b);
+        return LH_OK;
+    }
+    // Dry runs on the first samples of every graph (step size scaled to zero).
+    unsigned long long probe = 0;
+    for (auto *h : b->hs) probe += h->p.total_samples;
+    probe = probe / (unsigned long long)b->G / 50 + 4096;
+    const int bpcs[] = {4, 8, 16};
+    const unsigned long long items[] = {2048, 8192, 32768};
+    float best = 1e30f;
+    int bv = b->variant, bb = b->blocks_per_cu;
+    unsigned long long bi = b->item_samples;
+    for (int v = 0; v < 2; ++v)
+        for (int bpc : bpcs)
+            for (unsigned long long is : items) {
+                batch_items(b, is, true, probe);
+                if (upload_desc(b) != hipSuccess) return LH_ERR_HIP;
+                if (batch_launch_raw(b, v, bpc, is) != hipSuccess) return LH_ERR_HIP;  // warm-up
+                (void)hipEventRecord(b->ev0, b->stream);
+                (void)batch_launch_raw(b, v, bpc, is);
+                (void)hipEventRecord(b->ev1, b->stream);
+                if (hipEventSynchronize(b->ev1) != hipSuccess) return LH_ERR_HIP;
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+                if (ms < best) {
+                    best = ms;
+                    bv = v;
+                    bb = bpc;
+                    bi = is;
+                }
+            }
+    b->variant = bv;
+    b->blocks_per_cu = bb;
+    b->item_samples = bi;
+    batch_items(b, b->item_samples, false, 0);
+    if (upload_desc(b) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) return LH_ERR_HIP;
+    drop_graph(b);
+    int v4[4] = {bv, bb, (int)bi, 0};
+    cache_store(cache_path, key, v4);
+    return LH_OK;
+}
+
+lh_status lh_batch_capture(lh_batch *b)
+{
+    if (!b) return LH_ERR_INVALID_ARG;
+    drop_graph(b);
+    batch_items(b, b->item_samples, false, 0);
+    if (upload_desc(b) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) return LH_ERR_HIP;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LH_ERR_HIP;
+    hipError_t e = batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples);
+    hipError_t e2 = hipStreamEndCapture(b->stream, &b->graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        drop_graph(b);
+        return LH_ERR_HIP;
+    }
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        drop_graph(b);
+        return LH_ERR_HIP;
+    }
+    return LH_OK;
+}
+
+lh_status lh_batch_launch(lh_batch *b)
+{
+    if (!b) return LH_ERR_INVALID_ARG;
+    if (!b->exec) return LH_ERR_NOT_BUILT;
+    (void)hipEventRecord(b->ev0, b->stream);
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return LH_ERR_HIP;
+    (void)hipEventRecord(b->ev1, b->stream);
+    b->timed = true;
+    return LH_OK;
+}
+
+lh_status lh_batch_run(lh_batch *b)
+{
+    if (!b) return LH_ERR_INVALID_ARG;
+    batch_items(b, b->item_samples, false, 0);
+    if (upload_desc(b) != hipSuccess) return LH_ERR_HIP;
+    (void)hipEventRecord(b->ev0, b->stream);
+    if (batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples) != hipSuccess) return LH_ERR_HIP;
+    (void)hipEventRecord(b->ev1, b->stream);
+    b->timed = true;
+    return LH_OK;
+}
+
+lh_status lh_batch_last_ms(lh_batch *b, double *ms)
+{
+    if (!b || !ms) return LH_ERR_INVALID_ARG;
+    *ms = 0;
+    if (!b->timed) return LH_OK;
+    if (hipEventSynchronize(b->ev1) != hipSuccess) return LH_ERR_HIP;
+    float f = 0;
+    if (hipEventElapsedTime(&f, b->ev0, b->ev1) != hipSuccess) return LH_ERR_HIP;
+    *ms = f;
+    return LH_OK;
+}
+
+lh_status lh_batch_done(lh_batch *b, uint64_t *done_per_graph)
+{
+    if (!b || !done_per_graph) return LH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return LH_ERR_HIP;
+    if (hipMemcpy(done_per_graph, b->d_ctr + 1, sizeof(unsigned long long) * b->G, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return LH_ERR_HIP;
+    return LH_OK;
+}
+
+lh_status lh_batch_destroy(lh_batch *b)
+{
+    if (!b) return LH_ERR_INVALID_ARG;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_ctr) (void)hipFree(b->d_ctr);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    delete b;
+    return LH_OK;
+}
+
+}  // extern "C"

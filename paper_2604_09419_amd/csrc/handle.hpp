@@ -1,0 +1,95 @@
+// Internal host-side state of a linehip handle and the workspace layouts.
+#pragma once
+
+#include <string>
+
+#include "common.hpp"
+
+namespace lh {
+
+// One graph as the training kernels see it (passed by value to kernels).
+struct GraphDev {
+    void *tab[3];              // U, C, U1 (binary32 or bfloat16), NULL when unused
+    const EdgeRec *erec;       // [m]
+    const NegRec *nrec;        // [n]
+    long long m, n;
+    unsigned long long seed;   // Philox key word 0
+    unsigned long long key1;   // Philox key word 1 for sampling (graph_id)
+    unsigned long long sr_key; // Philox key word 1 for stochastic-rounding bits
+    unsigned long long T;
+    double eta0;
+    float lambda, alpha;
+    float eta_scale;           // 1 for training, 0 for timing-only dry runs
+    int d, nch;                // width and number of 16-byte chunks per row
+    int K;
+};
+
+// A kernel configuration: lanes per sample and 16-byte chunks per lane.
+struct TileCfg {
+    int lps = 0, cpl = 0, blocks_per_cu = 0;
+};
+
+struct WsLayout {
+    size_t status = 0, erec = 0, nrec = 0;
+    size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, contrib = 0, hist = 0, ilev = 0,
+           seg = 0, segid = 0, total = 0;
+    long long entries = 0, hist_n = 0, ilev_n = 0;
+};
+
+struct ScratchLayout {
+    size_t wq = 0, dx = 0, idx = 0, lpos = 0, deg = 0, lev = 0, ilev = 0, total = 0;
+    long long N = 0, lev_n = 0;
+};
+
+WsLayout ws_layout(const lh_params &p, long long n, long long m);
+ScratchLayout scratch_layout(long long n, long long m);
+
+constexpr int RADIX_ITEMS = 16;
+constexpr int RADIX_THREADS = 256;
+constexpr int RADIX_TILE = RADIX_ITEMS * RADIX_THREADS;
+
+}  // namespace lh
+
+struct lh_handle {
+    lh_params p{};
+    int device = 0;
+    int num_cu = 256;
+    hipStream_t stream = nullptr;
+    bool bound = false, graph_set = false, edge_ready = false, neg_ready = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *tab[3] = {nullptr, nullptr, nullptr};
+    long long n = 0, m = 0;
+    const int32_t *src = nullptr, *dst = nullptr;
+    const float *w = nullptr;
+    lh::WsLayout lay;
+    EdgeRec *erec = nullptr;
+    NegRec *nrec = nullptr;
+    unsigned int *status = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    lh::TileCfg cfg;  // chosen Hogwild kernel configuration
+    std::string err;
+};
+
+namespace lh {
+lh::GraphDev graph_dev(const lh_handle *h);
+lh_status fail(lh_handle *h, lh_status s, const std::string &msg);
+lh_status hip_fail(lh_handle *h, hipError_t e, const char *what);
+
+// Kernel families (implemented in separate translation units).
+lh_status validate_graph(lh_handle *h);
+lh_status build_alias(lh_handle *h, void *scratch, size_t bytes);
+lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32_t *alias);
+lh_status export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias);
+void launch_init(lh_handle *h);
+void launch_sample(lh_handle *h, unsigned long long first, unsigned long long count, int32_t *u,
+                   int32_t *v, int32_t *neg);
+void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *buf, bool write);
+TileCfg default_cfg(int dtype, int d);
+bool cfg_supported(int dtype, int d, const TileCfg &c);
+hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c,
+                          unsigned long long first, unsigned long long end, int num_cu,
+                          unsigned int *status, hipStream_t s);
+lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count);
+}  // namespace lh

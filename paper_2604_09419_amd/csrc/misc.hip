@@ -1,0 +1,233 @@
+// Sampling (parity hook), initial values, table conversion, kernel dispatch and the
+// workspace layouts.
+#include "handle.hpp"
+#include "scan.hpp"
+#include "sgd_kernels.hpp"
+
+namespace lh {
+
+LH_DECLARE_LAUNCHERS(float, 1)
+LH_DECLARE_LAUNCHERS(float, 2)
+LH_DECLARE_LAUNCHERS(float, 3)
+LH_DECLARE_LAUNCHERS(uint16_t, 1)
+LH_DECLARE_LAUNCHERS(uint16_t, 2)
+LH_DECLARE_LAUNCHERS(uint16_t, 3)
+
+// ---------------------------------------------------------------------------
+// Workspace layouts.
+// ---------------------------------------------------------------------------
+static size_t carve(size_t &off, size_t bytes)
+{
+    size_t at = off;
+    off = lh_align_up(off + bytes, 256);
+    return at;
+}
+
+WsLayout ws_layout(const lh_params &p, long long n, long long m)
+{
+    WsLayout L;
+    size_t off = 0;
+    L.status = carve(off, 256);
+    L.erec = carve(off, sizeof(EdgeRec) * (size_t)(m > 0 ? m : 1));
+    L.nrec = carve(off, sizeof(NegRec) * (size_t)(n > 0 ? n : 1));
+    if (p.mode == LH_SNAPSHOT) {
+        long long nord = p.orders == 3 ? 2 : 1;
+        long long E = p.batch * nord * (long long)(p.K + 2);
+        L.entries = E;
+        L.keys0 = carve(off, 4 * (size_t)E);
+        L.keys1 = carve(off, 4 * (size_t)E);
+        L.vals0 = carve(off, 4 * (size_t)E);
+        L.vals1 = carve(off, 4 * (size_t)E);
+        L.contrib = carve(off, 4 * (size_t)E * (size_t)p.d);
+        L.hist_n = 16 * LH_CDIV(E, RADIX_TILE);
+        L.hist = carve(off, 4 * (size_t)L.hist_n);
+        long long mx = L.hist_n > E ? L.hist_n : E;
+        L.ilev_n = scan_levels_size(mx);
+        L.ilev = carve(off, 4 * (size_t)L.ilev_n);
+        L.seg = carve(off, 4 * (size_t)(E + 1));
+        L.segid = carve(off, 4 * (size_t)(E + 1));
+    }
+    L.total = off;
+    return L;
+}
+
+ScratchLayout scratch_layout(long long n, long long m)
+{
+    ScratchLayout L;
+    long long N = n > m ? n : m;
+    if (N < 1) N = 1;
+    L.N = N;
+    size_t off = 0;
+    L.wq = carve(off, 8 * (size_t)N);
+    L.dx = carve(off, 8 * (size_t)N);
+    L.idx = carve(off, 4 * (size_t)N);
+    L.lpos = carve(off, 4 * (size_t)N);
+    L.deg = carve(off, 4 * (size_t)(n > 0 ? n : 1));
+    L.lev_n = scan_levels_size(N);
+    L.lev = carve(off, 8 * (size_t)L.lev_n);
+    L.ilev = carve(off, 4 * (size_t)L.lev_n);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel configurations.
+// ---------------------------------------------------------------------------
+static int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+TileCfg default_cfg(int dtype, int d)
+{
+    const int vec = dtype == LH_FP32 ? 4 : 8;
+    const int nch = d / vec;
+    TileCfg c;
+    c.lps = next_pow2(nch);
+    if (c.lps < 2) c.lps = 2;
+    c.cpl = 1;
+    if (c.lps > 64) {
+        c.lps = 64;
+        c.cpl = LH_CDIV(nch, 64);
+    }
+    c.blocks_per_cu = 8;
+    return c;
+}
+
+bool cfg_supported(int dtype, int d, const TileCfg &c)
+{
+    const int vec = dtype == LH_FP32 ? 4 : 8;
+    const int nch = d / vec;
+    bool listed = false;
+#define LH_CHECK_CFG(L, C) listed = listed || (c.lps == L && c.cpl == C);
+    LH_CFG_LIST(LH_CHECK_CFG)
+#undef LH_CHECK_CFG
+    return listed && c.lps * c.cpl >= nch && c.blocks_per_cu >= 1 && c.blocks_per_cu <= 64;
+}
+
+hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c, unsigned long long first,
+                          unsigned long long end, int num_cu, unsigned int *, hipStream_t s)
+{
+    if (dtype == LH_FP32) {
+        if (orders == 1) return launch_hogwild_t<float, 1>(g, c, first, end, num_cu, s);
+        if (orders == 2) return launch_hogwild_t<float, 2>(g, c, first, end, num_cu, s);
+        return launch_hogwild_t<float, 3>(g, c, first, end, num_cu, s);
+    }
+    if (orders == 1) return launch_hogwild_t<uint16_t, 1>(g, c, first, end, num_cu, s);
+    if (orders == 2) return launch_hogwild_t<uint16_t, 2>(g, c, first, end, num_cu, s);
+    return launch_hogwild_t<uint16_t, 3>(g, c, first, end, num_cu, s);
+}
+
+// ---------------------------------------------------------------------------
+// Sampling: one thread per sample, the same draw as phase A of the training tile.
+// ---------------------------------------------------------------------------
+__global__ void k_sample(GraphDev g, unsigned long long first, unsigned long long count, int32_t *u, int32_t *v,
+                         int32_t *neg)
+{
+    unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const unsigned long long s = first + i;
+    u64x4 x = philox4x64_10(g.seed, g.key1, s, 0ull, 0ull, 0ull);
+    long long ce = draw_column(x.x, g.m);
+    EdgeRec r = g.erec[ce];
+    bool keep = x.y < r.thr;
+    u[i] = keep ? r.src_c : r.src_a;
+    v[i] = keep ? r.dst_c : r.dst_a;
+    for (int j = 1; j <= g.K; ++j) {
+        u64x4 y = philox4x64_10(g.seed, g.key1, s, (unsigned long long)j, 0ull, 0ull);
+        long long cn = draw_column(y.x, g.n);
+        NegRec nr = g.nrec[cn];
+        neg[i * (unsigned long long)g.K + (j - 1)] = y.y < nr.thr ? (int32_t)cn : nr.alias;
+    }
+}
+
+void launch_sample(lh_handle *h, unsigned long long first, unsigned long long count, int32_t *u, int32_t *v,
+                   int32_t *neg)
+{
+    GraphDev g = graph_dev(h);
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)LH_CDIV(count, 256)), dim3(256), 0, h->stream, g, first, count, u,
+                       v, neg);
+}
+
+// ---------------------------------------------------------------------------
+// Initial values: element (t, r, c) = word c % 4 of Philox4x64-10 with key
+// (seed, 2^32 | graph_id) and counter (r, c / 4, t, 0); value ((x >> 40) - 2^23)
+// 2^-24 / d in binary64, rounded once to binary32 (bfloat16: then to nearest even).
+// ---------------------------------------------------------------------------
+template <typename TT>
+__global__ void k_init(TT *X, int t, long long rows, int d, unsigned long long seed, unsigned long long key1)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n4 = (d + 3) / 4;
+    if (i >= rows * n4) return;
+    long long r = i / n4;
+    int c4 = (int)(i % n4);
+    u64x4 x = philox4x64_10(seed, key1, (unsigned long long)r, (unsigned long long)c4, (unsigned long long)t, 0ull);
+    unsigned long long w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int c = c4 * 4 + k;
+        if (c >= d) break;
+        double val = ((double)((long long)(w[k] >> 40) - 8388608ll) * 0x1p-24) / (double)d;
+        float f = (float)val;
+        if constexpr (sizeof(TT) == 4)
+            X[r * d + c] = f;
+        else
+            X[r * d + c] = (uint16_t)f32_to_bf16_rne(f);
+    }
+}
+
+void launch_init(lh_handle *h)
+{
+    const lh_params &p = h->p;
+    unsigned long long key1 = (1ull << 32) | (unsigned long long)(uint32_t)p.graph_id;
+    long long work = h->n * ((p.d + 3) / 4);
+    for (int t = 0; t < 3; ++t) {
+        if (!h->tab[t]) continue;
+        if (p.dtype == LH_FP32)
+            hipLaunchKernelGGL(k_init<float>, dim3((unsigned)LH_CDIV(work, 256)), dim3(256), 0, h->stream,
+                               (float *)h->tab[t], t, h->n, p.d, p.seed, key1);
+        else
+            hipLaunchKernelGGL(k_init<uint16_t>, dim3((unsigned)LH_CDIV(work, 256)), dim3(256), 0, h->stream,
+                               (uint16_t *)h->tab[t], t, h->n, p.d, p.seed, key1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Table <-> binary32 buffer.
+// ---------------------------------------------------------------------------
+template <typename TT>
+__global__ void k_rw(TT *X, long long off, long long count, float *buf, int write)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    if (write) {
+        if constexpr (sizeof(TT) == 4)
+            X[off + i] = buf[i];
+        else
+            X[off + i] = (uint16_t)f32_to_bf16_rne(buf[i]);
+    } else {
+        if constexpr (sizeof(TT) == 4)
+            buf[i] = X[off + i];
+        else
+            buf[i] = bf16_bits_to_f32(X[off + i]);
+    }
+}
+
+void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *buf, bool write)
+{
+    long long count = rows * h->p.d, off = row0 * h->p.d;
+    if (count <= 0) return;
+    dim3 grid((unsigned)LH_CDIV(count, 256));
+    if (h->p.dtype == LH_FP32)
+        hipLaunchKernelGGL(k_rw<float>, grid, dim3(256), 0, h->stream, (float *)h->tab[table], off, count, buf,
+                           write ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_rw<uint16_t>, grid, dim3(256), 0, h->stream, (uint16_t *)h->tab[table], off, count,
+                           buf, write ? 1 : 0);
+}
+
+}  // namespace lh

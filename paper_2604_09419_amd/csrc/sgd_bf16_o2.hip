@@ -1,0 +1,6 @@
+// Instantiation of the Hogwild and SNAPSHOT-contribution kernels for bf16 tables, orders = 2.
+#include "sgd_kernels.hpp"
+
+namespace lh {
+LH_DEFINE_LAUNCHERS(uint16_t, 2)
+}  // namespace lh

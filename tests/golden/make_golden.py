@@ -1,0 +1,63 @@
+"""Write the stored expected values under tests/golden/ (calls only oracle/ and synth/).
+
+    python tests/golden/make_golden.py c1_auc    # seconds
+    python tests/golden/make_golden.py c2_auc    # about 35 minutes, single thread
+
+Each output JSON records the command, the workload and the oracle's binary64 result.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from synth import CONFIGS, config_graph  # noqa: E402
+
+
+def run_auc(name: str, orders: int, T: int, d: int, out: str):
+    cfg = CONFIGS[name]
+    t0 = time.time()
+    g, hs, hd, neg = config_graph(name, holdout=True)
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+    m = oracle.Model(tb, d=d, K=cfg["K"], orders=orders, T=T, seed=cfg["seed"],
+                     eta0=cfg["eta0"])
+    res = {"workload": name, "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": d,
+           "K": cfg["K"], "orders": orders, "T": T, "seed": cfg["seed"], "eta0": cfg["eta0"],
+           "mode": "seq", "precision": "binary64",
+           "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    def aucs(prefix):
+        """Held-out AUC under each score: order 2 vertex.context (uc) and
+        vertex.vertex (uu), order 1 (o1), and the concatenated embedding (concat)."""
+        sc = {}
+        if orders & 2:
+            sc["uc"] = (m.scores(hs, hd, 2), m.scores(hs, neg, 2))
+            sc["uu"] = (oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg))
+        if orders & 1:
+            sc["o1"] = (m.scores(hs, hd, 1), m.scores(hs, neg, 1))
+        if orders == 3:
+            sc["concat"] = (sc["uu"][0] + sc["o1"][0], sc["uu"][1] + sc["o1"][1])
+        for k, (p, q) in sc.items():
+            res[f"{prefix}auc_{k}"] = oracle.auc(p, q)
+
+    aucs("init_")
+    m.train(0, T, "seq")
+    aucs("")
+    res["oracle_seconds"] = round(time.time() - t0, 1)
+    with open(os.path.join(HERE, out), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    which = sys.argv[1]
+    if which == "c1_auc":
+        run_auc("C1", orders=2, T=CONFIGS["C1"]["T"], d=CONFIGS["C1"]["d"], out="c1_oracle_auc.json")
+    elif which == "c2_auc":
+        run_auc("C2", orders=3, T=CONFIGS["C2"]["T"], d=CONFIGS["C2"]["d"], out="c2_oracle_auc.json")
+    else:
+        raise SystemExit(__doc__)

@@ -1,0 +1,261 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the GPU.
+
+Integer work (alias tables, sampled IDs) must match bit for bit; the deterministic
+SNAPSHOT mode must agree with the binary64 oracle within 1e-5 relative error per row;
+the Hogwild mode must match the oracle's held-out AUC within 0.005.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_graph
+from synth.graphs import Graph
+
+from gpu_util import dot_rows, fro_rel_err, max_row_rel_err, trainer_for
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _lh():
+    import paper_2604_09419_amd as lh
+    return lh
+
+
+def _rand_graph(n, m, seed, weights="lognormal", zero_frac=0.0):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, size=m).astype(np.int32)
+    dst = rng.integers(0, n, size=m).astype(np.int32)
+    if weights == "unit":
+        w = np.ones(m, np.float32)
+    else:
+        w = rng.lognormal(0, 1.5, size=m).astype(np.float32)
+    if zero_frac:
+        w[rng.random(m) < zero_frac] = 0.0
+    return Graph(n=n, src=src, dst=dst, w=w)
+
+
+def _alias_equal(tr, t):
+    lh = _lh()
+    ethr, eal = tr.export_alias(lh.LH_ALIAS_EDGE)
+    nthr, nal = tr.export_alias(lh.LH_ALIAS_NEG)
+    assert np.array_equal(eal, t.ealias) and np.array_equal(ethr, t.ethr)
+    assert np.array_equal(nal, t.nalias) and np.array_equal(nthr, t.nthr)
+
+
+# ---------------------------------------------------------------------------
+# Alias tables: bitwise equal to the oracle's.
+# ---------------------------------------------------------------------------
+def test_alias_tables_c1(c1_graph, c1_tables):
+    tr = trainer_for(c1_graph, d=16, total_samples=10, init=False)
+    _alias_equal(tr, c1_tables)
+
+
+@pytest.mark.parametrize("case", ["one_arc", "uniform", "zeros", "ragged1025", "ragged3001", "multilevel",
+                                  "one_heavy"])
+def test_alias_tables_edge_cases(case):
+    if case == "one_arc":
+        g = Graph(n=1, src=np.zeros(1, np.int32), dst=np.zeros(1, np.int32), w=np.ones(1, np.float32))
+    elif case == "uniform":
+        g = _rand_graph(300, 1000, 1, weights="unit")
+    elif case == "zeros":
+        g = _rand_graph(500, 4000, 2, zero_frac=0.3)
+    elif case == "ragged1025":
+        g = _rand_graph(777, 1025, 3)
+    elif case == "ragged3001":
+        g = _rand_graph(5000, 3001, 4)
+    elif case == "multilevel":
+        g = _rand_graph(200_000, 1024 * 1024 + 17, 5)
+    else:
+        g = _rand_graph(1000, 5000, 6)
+        g.w[17] = 1e6
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    tr = trainer_for(g, d=16, total_samples=10, init=False)
+    _alias_equal(tr, t)
+
+
+def test_negative_table_every_degree_up_to_4095():
+    """Node i has i out-arcs, so every degree 0..4095 passes through d^0.75 on the GPU."""
+    n = 4096
+    deg = np.arange(n)
+    src = np.repeat(np.arange(n, dtype=np.int32), deg)
+    rng = np.random.default_rng(7)
+    dst = rng.integers(0, n, size=src.size).astype(np.int32)
+    g = Graph(n=n, src=src, dst=dst, w=np.ones(src.size, np.float32))
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    tr = trainer_for(g, d=16, total_samples=10, init=False)
+    _alias_equal(tr, t)
+
+
+# ---------------------------------------------------------------------------
+# Sampler: bit-exact IDs.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("first,count", [(0, 100_003), (2**32 - 50_000, 100_000), (2**40 + 7, 4097)])
+def test_sampler_bit_exact(c1_graph, c1_tables, first, count):
+    lh = _lh()
+    tr = trainer_for(c1_graph, d=16, K=5, seed=1234, total_samples=10, init=False)
+    u, v, neg = tr.sample(first, count)
+    ou, ov, oneg = oracle.sample(c1_tables, seed=1234, graph_id=0, K=5, first=first, count=count)
+    assert np.array_equal(u.cpu().numpy(), ou)
+    assert np.array_equal(v.cpu().numpy(), ov)
+    assert np.array_equal(neg.cpu().numpy(), oneg)
+    # the same draws from tables imported from the oracle
+    tr.import_alias(lh.LH_ALIAS_EDGE, c1_tables.ethr.view(np.int64), c1_tables.ealias)
+    tr.import_alias(lh.LH_ALIAS_NEG, c1_tables.nthr.view(np.int64), c1_tables.nalias)
+    tr.check()
+    u2, v2, n2 = tr.sample(first, count)
+    assert np.array_equal(u2.cpu().numpy(), ou) and np.array_equal(n2.cpu().numpy(), oneg)
+
+
+def test_sampler_graph_ids_and_k(c1_graph, c1_tables):
+    tr = trainer_for(c1_graph, d=16, K=3, seed=5, graph_id=9, total_samples=10, init=False)
+    u, v, neg = tr.sample(123, 5000)
+    ou, ov, oneg = oracle.sample(c1_tables, seed=5, graph_id=9, K=3, first=123, count=5000)
+    assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(neg.cpu().numpy(), oneg)
+
+
+# ---------------------------------------------------------------------------
+# Initial values.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [16, 24, 128])
+def test_init_bitwise(d):
+    import torch
+    lh = _lh()
+    g = _rand_graph(1000, 3000, 8)
+    for dtype in ("fp32", "bf16"):
+        tr = trainer_for(g, d=d, orders=3, dtype=dtype, seed=77, graph_id=3, total_samples=10)
+        for t in (lh.LH_TABLE_U, lh.LH_TABLE_C, lh.LH_TABLE_U1):
+            ref = oracle.init_table(t, g.n, d, 77, 3)
+            got = tr.read(t).cpu().numpy()
+            if dtype == "fp32":
+                assert np.array_equal(got, ref)
+            else:
+                assert np.array_equal(got, torch.tensor(ref).to(torch.bfloat16).float().numpy())
+
+
+# ---------------------------------------------------------------------------
+# SNAPSHOT: binary32 GPU vs binary64 oracle.
+# ---------------------------------------------------------------------------
+def _snapshot_pair(g, t, d, K, orders, T, B, count, seed=1):
+    lh = _lh()
+    tr = trainer_for(g, d=d, K=K, orders=orders, seed=seed, total_samples=T, mode="snapshot", batch=B)
+    tr.train_steps(0, count)
+    tr.check()
+    m = oracle.Model(t, d=d, K=K, orders=orders, T=T, seed=seed)
+    m.train(0, count, "snapshot", B)
+    out = {}
+    for name, tab, ref in (("U", lh.LH_TABLE_U, m.U), ("C", lh.LH_TABLE_C, m.C), ("U1", lh.LH_TABLE_U1, m.U1)):
+        if ref is not None:
+            out[name] = (tr.read(tab).cpu().numpy(), ref)
+    return tr, out
+
+
+@pytest.mark.parametrize("B,count", [(1, 20_000), (256, 1_000_000), (65536, 1_000_000)])
+def test_snapshot_c1_within_1e5(c1_graph, c1_tables, B, count):
+    _, out = _snapshot_pair(c1_graph, c1_tables, d=16, K=5, orders=2, T=1_000_000, B=B, count=count)
+    for name, (x, ref) in out.items():
+        err = max_row_rel_err(x, ref)
+        print(f"snapshot C1 B={B} table {name}: max row rel err {err:.3e}", flush=True)
+        assert err <= 1e-5, (name, err)
+
+
+def test_snapshot_orders12_ragged_batches(c1_graph, c1_tables):
+    _, out = _snapshot_pair(c1_graph, c1_tables, d=32, K=5, orders=3, T=300_000, B=1000, count=300_000)
+    for name, (x, ref) in out.items():
+        err = max_row_rel_err(x, ref)
+        print(f"snapshot C1 orders 1+2 d=32 table {name}: {err:.3e}", flush=True)
+        assert err <= 1e-5, (name, err)
+
+
+def test_snapshot_deterministic_and_resumable(c1_graph):
+    lh = _lh()
+    kw = dict(d=16, K=5, orders=3, seed=3, total_samples=200_000, mode="snapshot", batch=4096)
+    a = trainer_for(c1_graph, **kw)
+    b = trainer_for(c1_graph, **kw)
+    c = trainer_for(c1_graph, **kw)
+    a.train_steps(0, 200_000)
+    b.train_steps(0, 200_000)
+    c.train_steps(0, 4096 * 20)
+    saved = {t: c.read(t).cpu().numpy() for t in (lh.LH_TABLE_U, lh.LH_TABLE_C, lh.LH_TABLE_U1)}
+    c2 = trainer_for(c1_graph, **kw)
+    for t, x in saved.items():
+        c2.write(t, x)
+    c2.train_steps(4096 * 20, 200_000 - 4096 * 20)
+    for t in (lh.LH_TABLE_U, lh.LH_TABLE_C, lh.LH_TABLE_U1):
+        xa = a.read(t).cpu().numpy()
+        assert np.array_equal(xa, b.read(t).cpu().numpy())
+        assert np.array_equal(xa, c2.read(t).cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# Hogwild: held-out AUC against the oracle's.
+# ---------------------------------------------------------------------------
+def test_hogwild_c1_auc_matches_oracle():
+    lh = _lh()
+    gold = json.load(open(os.path.join(GOLDEN, "c1_oracle_auc.json")))
+    g, hs, hd, neg = config_graph("C1", holdout=True)
+    tr = trainer_for(g, d=16, K=5, orders=2, seed=gold["seed"], total_samples=gold["T"])
+    tr.train_steps(0, gold["T"])
+    tr.check()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    auc_uc = oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg))
+    auc_uu = oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
+    print(f"C1 hogwild AUC uc {auc_uc:.4f} (oracle {gold['auc_uc']:.4f}) "
+          f"uu {auc_uu:.4f} (oracle {gold['auc_uu']:.4f})", flush=True)
+    assert abs(auc_uc - gold["auc_uc"]) <= 0.005
+    assert abs(auc_uu - gold["auc_uu"]) <= 0.005
+
+
+# ---------------------------------------------------------------------------
+# Error paths forced from the host.
+# ---------------------------------------------------------------------------
+def test_bad_graphs_are_rejected():
+    lh = _lh()
+    g = _rand_graph(100, 500, 9)
+    bad = Graph(n=100, src=g.src.copy(), dst=g.dst.copy(), w=g.w.copy())
+    bad.dst[7] = 100
+    with pytest.raises(lh.LhError) as e:
+        trainer_for(bad, d=16, total_samples=10)
+    assert e.value.status == 2
+    bad = Graph(n=100, src=g.src.copy(), dst=g.dst.copy(), w=g.w.copy())
+    bad.w[3] = -1.0
+    with pytest.raises(lh.LhError) as e:
+        trainer_for(bad, d=16, total_samples=10)
+    assert e.value.status == 3
+    bad.w[3] = np.nan
+    with pytest.raises(lh.LhError) as e:
+        trainer_for(bad, d=16, total_samples=10)
+    assert e.value.status == 3
+    zero = Graph(n=100, src=g.src, dst=g.dst, w=np.zeros(500, np.float32))
+    with pytest.raises(lh.LhError) as e:
+        trainer_for(zero, d=16, total_samples=10)
+    assert e.value.status == 3
+
+
+def test_state_and_range_errors(c1_graph, c1_tables):
+    lh = _lh()
+    tr = trainer_for(c1_graph, d=16, total_samples=1000, build=False, init=False)
+    with pytest.raises(lh.LhError) as e:
+        tr.train_steps(0, 10)
+    assert e.value.status == 5
+    tr.build_alias()
+    with pytest.raises(lh.LhError) as e:
+        tr.train_steps(990, 20)
+    assert e.value.status == 1
+    bad_alias = c1_tables.nalias.copy()
+    bad_alias[5] = c1_graph.n + 3
+    tr.import_alias(lh.LH_ALIAS_NEG, c1_tables.nthr.view(np.int64), bad_alias)
+    with pytest.raises(lh.LhError) as e:
+        tr.check()
+    assert e.value.status == 2
+    tr.check()  # the flag was cleared
+    u, v, neg = tr.sample(0, 10_000)
+    assert int(neg.max()) < c1_graph.n
+    s = trainer_for(c1_graph, d=16, total_samples=1000, mode="snapshot", batch=100)
+    with pytest.raises(lh.LhError) as e:
+        s.train_steps(50, 100)
+    assert e.value.status == 1
