@@ -143,17 +143,125 @@ def cpu_baseline(cfg, g, seed, target_s=15.0):
                       f"{threads} OpenMP threads; alias build and init excluded"}
 
 
+def bench_batched(args):
+    """C4: 64 power-law graphs (bfloat16, second order, d in {64, 128}) trained in one
+    persistent hipGraph-captured launch, against 64 one-graph launches."""
+    import torch
+    from paper_2604_09419_amd import BatchTrainer, Trainer
+    from synth import batch_graph_specs
+    from synth.graphs import rmat_graph_gpu
+    specs = batch_graph_specs()
+    stream = torch.cuda.Stream()
+    trainers = []
+    t0 = time.time()
+    for sp in specs:
+        src, dst, w = rmat_graph_gpu(sp["scale"], sp["n"], sp["m"], sp["seed"] + 100_000)
+        tr = Trainer(sp["n"], src, dst, w, d=sp["d"], K=5, orders=2, dtype="bf16", seed=sp["seed"],
+                     graph_id=sp["g"], total_samples=sp["T"], stream=stream)
+        trainers.append(tr)
+    torch.cuda.synchronize()
+    log(f"[bench] C4: 64 graphs generated and built in {time.time() - t0:.1f}s")
+    total_T = sum(sp["T"] for sp in specs)
+    algo_bytes = sum(sp["T"] * algorithmic_bytes_per_sample(sp["d"], 5, 2, 2) for sp in specs)
+    bt = BatchTrainer(trainers)
+    bt.tune(args.tune_cache)
+    bt.capture()
+    times = []
+    for i in range(args.warmup + args.steps):
+        for tr in trainers:
+            tr.init_embeddings()
+        bt.launch()
+        ms = bt.last_ms()
+        if i >= args.warmup:
+            times.append(ms)
+        log(f"[bench] C4 batched launch {i}: {ms:.1f} ms")
+    assert bt.done() == [sp["T"] for sp in specs]
+    seq_ms = 0.0
+    for tr in trainers:
+        tr.init_embeddings()
+        tr.train_steps(0, tr.T)
+        seq_ms += tr.last_train_ms()
+    ms = sum(times) / len(times)
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    return {
+        "metric": "edge samples/sec, 64 graphs in one persistent hipGraph launch (bf16)",
+        "value": total_T / (ms * 1e-3), "unit": "edge samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C4: 64 directed R-MAT graphs, n log-uniform 1e3..2e6, mean degree 8..32, "
+                               "lognormal weights, d in {64,128}, K=5, second order, bf16 tables, T_g = 20 m_g",
+                   "graphs": len(specs), "total_samples": total_T, "sum_m": sum(sp["m"] for sp in specs)},
+        "sequential_launches": {"ms": seq_ms, "samples_per_s": total_T / (seq_ms * 1e-3),
+                                "batched_speedup": seq_ms / ms},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_batch (bf16)"},
+    }
+
+
+def bench_large(args):
+    """C5: directed R-MAT scale 26 (2^26 nodes, 2^30 arcs), bfloat16, second order, 1e10 samples."""
+    import torch
+    from paper_2604_09419_amd import Trainer
+    from synth.graphs import rmat_graph_gpu
+    from synth import CONFIGS
+    cfg = CONFIGS["C5"]
+    t0 = time.time()
+    src, dst, w = rmat_graph_gpu(cfg["scale"], cfg["n"], cfg["m_unique"], cfg["seed"])
+    torch.cuda.synchronize()
+    log(f"[bench] C5 graph generated on the GPU in {time.time() - t0:.1f}s")
+    T = int(cfg["T"]) if args.c5_samples is None else int(args.c5_samples)
+    tr = Trainer(cfg["n"], src, dst, w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype="bf16",
+                 seed=cfg["seed"], total_samples=T, build=False, init=False)
+    del src, dst, w
+    tb = time.time()
+    tr.build_alias()
+    build_s = time.time() - tb
+    tr.init_embeddings()
+    tr.tune(probe=min(T, 50_000_000), cache_path=args.tune_cache)
+    tr.init_embeddings()
+    tr.train_steps(0, T)
+    ms = tr.last_train_ms()
+    tr.check()
+    bps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 2)
+    achieved = bps * T / (ms * 1e-3) / 1e9
+    return {
+        "metric": "edge samples/sec at d=128,K=5 (C5, bf16)", "value": T / (ms * 1e-3),
+        "unit": "edge samples/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C5: directed R-MAT scale 26, 67108864 nodes, 2^30 arcs, lognormal weights, "
+                               "d=128, K=5, second order, bf16 tables", "T": T,
+                   "kernel_config": tr.kernel_config(), "alias_build_s": build_s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_hogwild (bf16, order 2)",
+                     "bytes_per_sample": bps},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5"])
+    ap.add_argument("--c5-samples", type=float, default=None, help="override T for C5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "_work", "tune_cache.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2 GiB three times (HBM counter scale)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = 1 << 31
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": n}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -165,6 +273,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+
+    if args.workload == "C4":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "C5":
+        print(json.dumps(bench_large(args)), flush=True)
+        return
 
     cfg, g, hs, hd, neg = workload(args.workload)
     seed = cfg["seed"]

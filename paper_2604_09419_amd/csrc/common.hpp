@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/linehip.h"
+#include "linehip.h"
 
 // ---------------------------------------------------------------------------
 // Record layouts in HBM.

@@ -92,35 +92,51 @@ struct SnapOut {
     int nord;            // orders per sample (1 or 2)
 };
 
+// Sum over an aligned group of LPS lanes, every lane receiving the sum.  Within a row
+// of 16 lanes the butterfly uses DPP: quad_perm [1,0,3,2] and [2,3,0,1] (xor 1, 2), then
+// row_half_mirror and row_mirror, which pair each lane with a lane of the other half
+// once the halves are uniform.  Across rows: ds_swizzle xor 16, then a shuffle xor 32.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
+}
+
 template <int LPS>
 __device__ __forceinline__ float group_sum(float x)
 {
-#pragma unroll
-    for (int off = LPS / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    if constexpr (LPS >= 2) x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+    if constexpr (LPS >= 4) x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+    if constexpr (LPS >= 8) x += dpp_mov<0x141>(x);  // row_half_mirror
+    if constexpr (LPS >= 16) x += dpp_mov<0x140>(x); // row_mirror
+    if constexpr (LPS >= 32)
+        x += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
+    if constexpr (LPS >= 64) x += __shfl_xor(x, 32);
     return x;
 }
 
-// One order of one sample.  A holds the vertex rows, B the context rows (A == B for
-// first order).  ids[0] = v, ids[1..K] = negatives.
-template <typename TT, int LPS, int CPL, int KMAX, bool FIRST, bool SNAP>
-__device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u, const int (&ids)[KMAX + 1],
-                                          int K, float eta, unsigned dupb, unsigned dupu, uint32_t sr,
-                                          int oi, int gl, const SnapOut &so, unsigned long long s,
-                                          int tabA, int tabB)
+// This lane's chunks of the 2 + K rows of one order of one sample, as loaded.
+template <typename TT, int CPL, int KMAX>
+struct Rows {
+    float a[CPL][Elem<TT>::VEC];
+    float b[KMAX + 1][CPL][Elem<TT>::VEC];
+};
+
+template <typename TT, int LPS, int CPL, int KMAX>
+__device__ __forceinline__ void load_rows(Rows<TT, CPL, KMAX> &r, const GraphDev &g, const TT *A, const TT *B,
+                                          int u, const int (&ids)[KMAX + 1], int K, int gl)
 {
     constexpr int VEC = Elem<TT>::VEC;
     const int d = g.d, nch = g.nch;
-    float a[CPL][VEC];
-    float b[KMAX + 1][CPL][VEC];
     const TT *arow = A + (long long)u * d;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         int ch = c * LPS + gl;
         if (ch < nch) {
-            load_chunk<TT>(arow, ch, a[c]);
+            load_chunk<TT>(arow, ch, r.a[c]);
         } else {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) a[c][e] = 0.f;
+            for (int e = 0; e < VEC; ++e) r.a[c][e] = 0.f;
         }
     }
 #pragma unroll
@@ -130,13 +146,27 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
         for (int c = 0; c < CPL; ++c) {
             int ch = c * LPS + gl;
             if (j <= K && ch < nch) {
-                load_chunk<TT>(brow, ch, b[j][c]);
+                load_chunk<TT>(brow, ch, r.b[j][c]);
             } else {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) b[j][c][e] = 0.f;
+                for (int e = 0; e < VEC; ++e) r.b[j][c][e] = 0.f;
             }
         }
     }
+}
+
+// One order of one sample, rows already loaded.  A holds the vertex rows, B the context
+// rows (A == B for first order).  ids[0] = v, ids[1..K] = negatives.
+template <typename TT, int LPS, int CPL, int KMAX, bool FIRST, bool SNAP>
+__device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u, const int (&ids)[KMAX + 1],
+                                          int K, float eta, unsigned dupb, unsigned dupu, uint32_t sr,
+                                          int oi, int gl, const SnapOut &so, unsigned long long s,
+                                          int tabA, int tabB, const Rows<TT, CPL, KMAX> &rows)
+{
+    constexpr int VEC = Elem<TT>::VEC;
+    const int d = g.d, nch = g.nch;
+    const auto &a = rows.a;
+    const auto &b = rows.b;
     float gj[KMAX + 1];
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
@@ -151,7 +181,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
     for (int j = 0; j <= KMAX; ++j) gj[j] = group_sum<LPS>(gj[j]);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
-        float sg = 1.0f / (1.0f + __expf(-gj[j]));
+        float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-gj[j]));
         float gg = j == 0 ? eta * (1.0f - sg) : -eta * g.alpha * sg;
         gj[j] = j <= K ? gg : 0.f;
     }
@@ -309,31 +339,45 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
     int my_u = 0, my_ids[KMAX + 1];
     unsigned my_dup = 0;
     uint32_t my_sr = 0;
+    float my_eta = 0.f;
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) my_ids[j] = 0;
     {
         const unsigned long long s = tile + (unsigned long long)lane;
         if (s < end) {
+            // One Philox block at a time, its record load issued at once, so the loads of
+            // all 1 + K slots are in flight together while the blocks are not interleaved
+            // (which would hold 1 + K blocks of state in registers).
             u64x4 x0 = philox4x64_10(g.seed, g.key1, s, 0ull, 0ull, 0ull);
-            u64x4 xn[KMAX];
-#pragma unroll
-            for (int j = 0; j < KMAX; ++j)
-                if (j < K) xn[j] = philox4x64_10(g.seed, g.key1, s, (unsigned long long)(j + 1), 0ull, 0ull);
             long long ce = draw_column(x0.x, g.m);
             const uint4 *er = reinterpret_cast<const uint4 *>(g.erec + ce);
             uint4 r0 = er[0], r1 = er[1];
-            unsigned long long ethr = (unsigned long long)r0.x | ((unsigned long long)r0.y << 32);
-            bool keep = x0.y < ethr;
-            my_u = keep ? (int)r0.w : (int)r1.y;
-            my_ids[0] = keep ? (int)r1.x : (int)r1.z;
+            const unsigned long long x0y = x0.y;
             my_sr = (uint32_t)x0.z;
+            __builtin_amdgcn_sched_barrier(0);
+            unsigned long long xy[KMAX];
+            int cn[KMAX];
+            uint4 nr[KMAX];
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 if (j < K) {
-                    long long cn = draw_column(xn[j].x, g.n);
-                    uint4 nr = *reinterpret_cast<const uint4 *>(g.nrec + cn);
-                    unsigned long long nthr = (unsigned long long)nr.x | ((unsigned long long)nr.y << 32);
-                    my_ids[j + 1] = xn[j].y < nthr ? (int)cn : (int)nr.z;
+                    u64x4 x = philox4x64_10(g.seed, g.key1, s, (unsigned long long)(j + 1), 0ull, 0ull);
+                    cn[j] = (int)draw_column(x.x, g.n);
+                    xy[j] = x.y;
+                    nr[j] = *reinterpret_cast<const uint4 *>(g.nrec + cn[j]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            my_eta = (float)(g.eta0 * (1.0 - (double)s / (double)g.T)) * g.eta_scale;
+            unsigned long long ethr = (unsigned long long)r0.x | ((unsigned long long)r0.y << 32);
+            bool keep = x0y < ethr;
+            my_u = keep ? (int)r0.w : (int)r1.y;
+            my_ids[0] = keep ? (int)r1.x : (int)r1.z;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                if (j < K) {
+                    unsigned long long nthr = (unsigned long long)nr[j].x | ((unsigned long long)nr[j].y << 32);
+                    my_ids[j + 1] = xy[j] < nthr ? cn[j] : (int)nr[j].z;
                 }
             }
             // repeated rows among (v, n_1..n_K) in the low half, rows equal to u in the high half
@@ -358,20 +402,27 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
         const unsigned dup = (unsigned)__shfl((int)my_dup, src);
         uint32_t sr = 0;
         if constexpr (sizeof(TT) == 2 && !SNAP) sr = (uint32_t)__shfl((int)my_sr, src);
+        const float eta = __shfl(my_eta, src);  // every cross-lane read before lanes diverge
         const unsigned long long s = tile + (unsigned long long)src;
         if (s >= end) continue;
-        const float eta = (float)(g.eta0 * (1.0 - (double)s / (double)g.T)) * g.eta_scale;
         const unsigned dupb = dup & 0xffffu, dupu = dup >> 16;
+        // Issue the row loads of both orders before any arithmetic or store, so that up to
+        // 2 (2 + K) rows per sample are in flight at once.
+        Rows<TT, CPL, KMAX> r2, r1;
+        if constexpr ((ORD & 2) != 0)
+            load_rows<TT, LPS, CPL, KMAX>(r2, g, (const TT *)g.tab[0], (const TT *)g.tab[1], u, ids, K, gl);
+        if constexpr ((ORD & 1) != 0)
+            load_rows<TT, LPS, CPL, KMAX>(r1, g, (const TT *)g.tab[2], (const TT *)g.tab[2], u, ids, K, gl);
         int oi = 0;
         if constexpr ((ORD & 2) != 0) {
             sgd_order<TT, LPS, CPL, KMAX, false, SNAP>(g, (TT *)g.tab[0], (TT *)g.tab[1], u, ids, K, eta, dupb,
-                                                       dupu, sr, oi, gl, so, s, LH_TABLE_U, LH_TABLE_C);
+                                                       dupu, sr, oi, gl, so, s, LH_TABLE_U, LH_TABLE_C, r2);
             ++oi;
         }
         if constexpr ((ORD & 1) != 0) {
             sgd_order<TT, LPS, CPL, KMAX, true, SNAP>(g, (TT *)g.tab[2], (TT *)g.tab[2], u, ids, K, eta, dupb,
                                                       dupu, sr ^ 0x5bd1e995u, oi, gl, so, s, LH_TABLE_U1,
-                                                      LH_TABLE_U1);
+                                                      LH_TABLE_U1, r1);
         }
     }
 }

@@ -192,6 +192,63 @@ def batch_graph_specs(G: int = 64, base_seed: int = 4000, n_lo: float = 1e3, n_h
     return specs
 
 
+def rmat_graph_gpu(scale: int, n: int, m_unique: int, seed: int, weights: str = "lognormal",
+                   abc=RMAT_ABC, device: str = "cuda"):
+    """Directed R-MAT graph built on the GPU with torch (for graphs too large for numpy,
+    e.g. 2^30 arcs).  Same recipe as ``rmat_graph`` (quadrant draws per level, rejection
+    of self-loops and IDs >= n, first occurrence kept, exact m, seeded relabelling,
+    lognormal weights), with torch's seeded CUDA generator as the source of randomness.
+    Returns torch tensors (src int32, dst int32, w float32) on ``device``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    a, b, c = abc
+    keys = torch.empty(0, dtype=torch.int64, device=device)
+    need = m_unique
+    chunk = 1 << 27
+    while True:
+        parts = []
+        todo = int(need * 1.15) + 4096
+        while todo > 0:
+            cnt = min(chunk, todo)
+            u = torch.zeros(cnt, dtype=torch.int64, device=device)
+            v = torch.zeros(cnt, dtype=torch.int64, device=device)
+            for lvl in range(scale):
+                r = torch.rand(cnt, generator=gen, device=device)
+                sbit = r >= (a + b)
+                dbit = ((r >= a) & (r < a + b)) | (r >= a + b + c)
+                u |= sbit.to(torch.int64) << lvl
+                v |= dbit.to(torch.int64) << lvl
+                del r, sbit, dbit
+            keep = (u < n) & (v < n) & (u != v)
+            parts.append((u[keep] * n + v[keep]))
+            del u, v, keep
+            todo -= cnt
+        allk = torch.cat([keys] + parts)
+        del parts
+        # keep the first occurrence of every key, in generation order
+        sk, order = torch.sort(allk, stable=True)
+        first = torch.ones_like(sk, dtype=torch.bool)
+        first[1:] = sk[1:] != sk[:-1]
+        idx = torch.sort(order[first]).values
+        del sk, order, first
+        keys = allk[idx]
+        del allk, idx
+        if keys.numel() >= m_unique:
+            keys = keys[:m_unique]
+            break
+        need = m_unique - keys.numel()
+    perm = torch.randperm(n, generator=gen, device=device)
+    src = perm[keys // n].to(torch.int32)
+    dst = perm[keys % n].to(torch.int32)
+    del keys, perm
+    if weights == "unit":
+        w = torch.ones(m_unique, dtype=torch.float32, device=device)
+    else:
+        w = torch.empty(m_unique, dtype=torch.float32, device=device).log_normal_(0.0, 1.0, generator=gen)
+    return src, dst, w
+
+
 def batch_graph(spec: dict) -> Graph:
     """One graph of the batched workload from its spec (directed R-MAT, lognormal)."""
     g = rmat_graph(spec["scale"], spec["n"], spec["m"], spec["seed"] + 100_000, True, "lognormal")

@@ -1,0 +1,153 @@
+"""The two extensions on the GPU: bfloat16 tables with stochastic rounding, and many
+graphs trained in one persistent, hipGraph-captured launch.  Also the tuner's dry runs."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_graph, rmat_graph
+from synth.graphs import holdout_split, auc_negatives
+
+from gpu_util import dot_rows, fro_rel_err, max_row_rel_err, trainer_for
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _lh():
+    import paper_2604_09419_amd as lh
+    return lh
+
+
+def _auc_uc_uu(tr, hs, hd, neg):
+    lh = _lh()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    return (oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg)),
+            oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg)))
+
+
+def test_bf16_hogwild_c1_auc_matches_oracle():
+    gold = json.load(open(os.path.join(GOLDEN, "c1_oracle_auc.json")))
+    g, hs, hd, neg = config_graph("C1", holdout=True)
+    tr = trainer_for(g, d=16, K=5, orders=2, dtype="bf16", seed=gold["seed"], total_samples=gold["T"])
+    tr.train_steps(0, gold["T"])
+    tr.check()
+    uc, uu = _auc_uc_uu(tr, hs, hd, neg)
+    print(f"C1 bf16 hogwild AUC uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} "
+          f"(oracle {gold['auc_uu']:.4f})", flush=True)
+    assert abs(uc - gold["auc_uc"]) <= 0.005 and abs(uu - gold["auc_uu"]) <= 0.005
+
+
+def test_bf16_zero_step_leaves_tables_bitwise():
+    """With eta0 = 0 every written value is already bfloat16, and stochastic rounding of an
+    exactly representable value returns it unchanged."""
+    lh = _lh()
+    g = rmat_graph(12, 3000, 30_000, seed=3)
+    for mode in ("hogwild", "snapshot"):
+        tr = trainer_for(g, d=64, K=5, orders=3, dtype="bf16", eta0=0.0, seed=4, total_samples=100_000,
+                         mode=mode, batch=4096)
+        before = [tr.read(t).cpu().numpy() for t in (0, 1, 2)]
+        tr.train_steps(0, 100_000 if mode == "hogwild" else 4096 * 10)
+        tr.check()
+        after = [tr.read(t).cpu().numpy() for t in (0, 1, 2)]
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
+
+
+def test_bf16_snapshot_embedding_error_is_small(c1_graph, c1_tables):
+    lh = _lh()
+    T, B = 1_000_000, 256
+    tr = trainer_for(c1_graph, d=16, K=5, orders=2, dtype="bf16", seed=1, total_samples=T, mode="snapshot",
+                     batch=B)
+    tr.train_steps(0, T)
+    m = oracle.Model(c1_tables, d=16, K=5, orders=2, T=T, seed=1)
+    m.train(0, T, "snapshot", B)
+    for tab, ref in ((lh.LH_TABLE_U, m.U), (lh.LH_TABLE_C, m.C)):
+        err = fro_rel_err(tr.read(tab).cpu().numpy(), ref)
+        print(f"C1 bf16 SNAPSHOT B={B} table {tab}: embedding error {err:.3e}", flush=True)
+        assert err < 0.05
+
+
+def test_tune_is_a_dry_run():
+    lh = _lh()
+    g = rmat_graph(12, 3000, 30_000, seed=5)
+    for dtype in ("fp32", "bf16"):
+        tr = trainer_for(g, d=128, K=5, orders=3, dtype=dtype, seed=6, total_samples=1_000_000)
+        before = [tr.read(t).cpu().numpy() for t in (0, 1, 2)]
+        tr.tune(probe=200_000)
+        after = [tr.read(t).cpu().numpy() for t in (0, 1, 2)]
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
+        cfg = tr.kernel_config()
+        assert cfg["lanes_per_sample"] * cfg["chunks_per_lane"] * (4 if dtype == "fp32" else 8) >= 128
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent launch.
+# ---------------------------------------------------------------------------
+def _small_batch(G=6, dtype="bf16"):
+    import torch
+    lh = _lh()
+    rng = np.random.default_rng(0)
+    stream = torch.cuda.Stream()
+    items = []
+    for gi in range(G):
+        n = int(rng.integers(2000, 20000))
+        m = int(n * rng.uniform(8, 16))
+        d = 64 if gi % 2 == 0 else 128
+        g = rmat_graph(int(np.ceil(np.log2(n))), n, m, seed=700 + gi)
+        tr_g, hs, hd = holdout_split(g, seed=800 + gi)
+        neg = auc_negatives(g.n, g.src, g.dst, hs, seed=900 + gi)
+        T = 20 * tr_g.m
+        tr = lh.Trainer(tr_g.n, tr_g.src, tr_g.dst, tr_g.w, d=d, K=5, orders=2, dtype=dtype, seed=10 + gi,
+                        graph_id=gi, total_samples=T, stream=stream)
+        items.append((tr_g, hs, hd, neg, T, d, tr))
+    return items
+
+
+def test_batched_launch_trains_every_sample_once_and_matches_single_runs():
+    lh = _lh()
+    items = _small_batch()
+    bt = lh.BatchTrainer([it[-1] for it in items])
+    bt.run()
+    done = bt.done()
+    assert done == [it[4] for it in items]
+    for gi, (g, hs, hd, neg, T, d, tr) in enumerate(items):
+        tr.check()
+        uc_b, uu_b = _auc_uc_uu(tr, hs, hd, neg)
+        single = trainer_for(g, d=d, K=5, orders=2, dtype="bf16", seed=10 + gi, graph_id=gi, total_samples=T)
+        single.train_steps(0, T)
+        uc_s, uu_s = _auc_uc_uu(single, hs, hd, neg)
+        print(f"graph {gi} (n={g.n}, d={d}): batched uc {uc_b:.4f} uu {uu_b:.4f}; "
+              f"single uc {uc_s:.4f} uu {uu_s:.4f}", flush=True)
+        assert abs(uu_b - uu_s) <= 0.01 and abs(uc_b - uc_s) <= 0.01
+
+
+def test_batched_graph_capture_replays():
+    lh = _lh()
+    items = _small_batch(G=4)
+    bt = lh.BatchTrainer([it[-1] for it in items])
+    bt.capture()
+    for rep in range(3):
+        bt.launch()
+        ms = bt.last_ms()
+        assert bt.done() == [it[4] for it in items], rep
+        assert ms > 0
+        for it in items:
+            x = it[-1].read(lh.LH_TABLE_U).cpu().numpy()
+            assert np.all(np.isfinite(x))
+
+
+def test_batched_tuner_is_a_dry_run():
+    lh = _lh()
+    items = _small_batch(G=3)
+    trs = [it[-1] for it in items]
+    before = [t.read(lh.LH_TABLE_C).cpu().numpy() for t in trs]
+    bt = lh.BatchTrainer(trs)
+    bt.tune()
+    after = [t.read(lh.LH_TABLE_C).cpu().numpy() for t in trs]
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
