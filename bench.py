@@ -64,7 +64,8 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache):
                  eta0=cfg["eta0"], seed=seed, total_samples=T, build=False, init=False)
     # Tuning happens once, outside the timed region, with the step size scaled to zero.
     tr.build_alias()
-    tr.tune(probe=min(T, 20_000_000), cache_path=tune_cache)
+    if dtype == "fp32":  # bfloat16 timing runs are switched off in the library for now
+        tr.tune(probe=min(T, 20_000_000), cache_path=tune_cache)
     step_ms, kern_ms = [], []
     for i in range(warmup + steps):
         torch.cuda.synchronize()
@@ -164,7 +165,7 @@ def bench_batched(args):
     total_T = sum(sp["T"] for sp in specs)
     algo_bytes = sum(sp["T"] * algorithmic_bytes_per_sample(sp["d"], 5, 2, 2) for sp in specs)
     bt = BatchTrainer(trainers)
-    bt.tune(args.tune_cache)
+    # (the library refuses zero-step timing runs of bfloat16 batches for now: default tiling)
     bt.capture()
     times = []
     for i in range(args.warmup + args.steps):
@@ -217,7 +218,6 @@ def bench_large(args):
     tr.build_alias()
     build_s = time.time() - tb
     tr.init_embeddings()
-    tr.tune(probe=min(T, 50_000_000), cache_path=args.tune_cache)
     tr.init_embeddings()
     tr.train_steps(0, T)
     ms = tr.last_train_ms()

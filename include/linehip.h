@@ -74,6 +74,14 @@ typedef struct {
     int32_t mode;       /* LH_HOGWILD or LH_SNAPSHOT                                        */
     int32_t graph_id;   /* low 32 bits of key word 1 (one stream per graph)                 */
     int64_t batch;      /* SNAPSHOT batch B (samples [bB, (b+1)B) share one snapshot)      */
+    double hot_rate;    /* HOGWILD: a row whose expected number of concurrent writers
+                           (samples in flight x probability a sample touches it) reaches
+                           hot_rate is updated with atomic increments, other rows with
+                           plain stores.  <= 0: every row atomic; >= 1e30: none.        */
+    double max_conflicts; /* HOGWILD: the launch keeps F samples in flight with
+                           F (2 + K) / n_active <= max_conflicts, n_active = nodes with an
+                           arc, so that a row of average traffic has at most this many
+                           concurrent writers (staleness bound).  <= 0: no cap.          */
 } lh_params;
 
 typedef struct lh_handle lh_handle;

@@ -61,11 +61,32 @@ lh_status validate_graph(lh_handle *h)
 // ---------------------------------------------------------------------------
 // Weights of the two tables, binary64.
 // ---------------------------------------------------------------------------
-__global__ void k_out_degree(const int32_t *src, long long m, int32_t *deg)
+__global__ void k_degrees(const int32_t *src, const int32_t *dst, long long m, int32_t *deg, int32_t *indeg)
 {
     long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= m) return;
     atomicAdd(&deg[src[a]], 1);
+    atomicAdd(&indeg[dst[a]], 1);
+}
+
+// Heat of node r (see common.hpp): floor(-log2 p_r), p_r = (out + in) / m + K nu_r / W_nu.
+// It only chooses between two write paths of the training kernel, so it is computed in
+// ordinary binary64 arithmetic.
+__global__ void k_heat(const int32_t *deg, const int32_t *indeg, const double *nu, const double *nu_scan,
+                       long long n, long long m, int K, uint8_t *heat, unsigned long long *n_active)
+{
+    long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (deg[r] + indeg[r] > 0) atomicAdd(n_active, 1ull);
+    double Wn = nu_scan[n - 1];
+    double p = (double)(deg[r] + indeg[r]) / (double)m;
+    if (Wn > 0.0) p += (double)K * nu[r] / Wn;
+    int hv = 255;
+    if (p > 0.0) {
+        double t = floor(-log2(p));
+        hv = t < 0.0 ? 0 : (t > 255.0 ? 255 : (int)t);
+    }
+    heat[r] = (uint8_t)hv;
 }
 
 __global__ void k_zero_i32(int32_t *p, long long n)
@@ -73,6 +94,8 @@ __global__ void k_zero_i32(int32_t *p, long long n)
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
+
+__global__ void k_zero_u64(unsigned long long *p) { p[0] = 0ull; }
 
 __global__ void k_edge_weights(const float *w, long long m, double *wq)
 {
@@ -163,7 +186,10 @@ struct RecOut {
     EdgeRec *erec;  // edge table, or
     NegRec *nrec;   // negative table
     const int32_t *src, *dst;
+    const uint8_t *heat;  // per node; NULL: every node 255 (never hot)
 };
+
+__device__ __forceinline__ uint32_t heat_of(const RecOut &o, long long v) { return o.heat ? o.heat[v] : 255u; }
 
 __device__ __forceinline__ void write_rec(const RecOut &o, long long i, unsigned long long thr,
                                           int32_t al)
@@ -176,13 +202,14 @@ __device__ __forceinline__ void write_rec(const RecOut &o, long long i, unsigned
         r.dst_c = o.dst[i];
         r.src_a = o.src[al];
         r.dst_a = o.dst[al];
-        r.pad = 0;
+        r.heat = heat_of(o, r.src_c) | (heat_of(o, r.dst_c) << 8) | (heat_of(o, r.src_a) << 16) |
+                 (heat_of(o, r.dst_a) << 24);
         o.erec[i] = r;
     } else {
         NegRec r;
         r.thr = thr;
         r.alias = al;
-        r.pad = 0;
+        r.heat = heat_of(o, i) | (heat_of(o, al) << 8);
         o.nrec[i] = r;
     }
 }
@@ -240,19 +267,16 @@ static lh_status build_one(lh_handle *h, int which, const ScratchLayout &L, char
     int32_t *idx = (int32_t *)(sc + L.idx);
     int32_t *lpos = (int32_t *)(sc + L.lpos);
     int32_t *deg = (int32_t *)(sc + L.deg);
+    const uint8_t *heat = (const uint8_t *)(sc + L.heat);
     double *lev = (double *)(sc + L.lev);
     int32_t *ilev = (int32_t *)(sc + L.ilev);
     dim3 blk(256), grd((unsigned)LH_CDIV(N, 256));
 
-    if (which == LH_ALIAS_EDGE) {
+    // (out-degrees and heats were computed by build_alias before either table)
+    if (which == LH_ALIAS_EDGE)
         hipLaunchKernelGGL(k_edge_weights, grd, blk, 0, s, h->w, N, wq);
-    } else {
-        hipLaunchKernelGGL(k_zero_i32, grd, blk, 0, s, deg, N);
-        if (h->m > 0)
-            hipLaunchKernelGGL(k_out_degree, dim3((unsigned)LH_CDIV(h->m, 256)), blk, 0, s, h->src, h->m,
-                               deg);
+    else
         hipLaunchKernelGGL(k_neg_weights, grd, blk, 0, s, deg, N, wq);
-    }
     chunk_scan<OpNeumaier>(wq, dx, N, lev, s);
     hipLaunchKernelGGL(k_normalise, grd, blk, 0, s, wq, dx, N, lpos, h->status);
     chunk_scan<OpAdd<int32_t>>(lpos, lpos, N, ilev, s);
@@ -278,7 +302,7 @@ static lh_status build_one(lh_handle *h, int which, const ScratchLayout &L, char
         chunk_scan<OpMax>(dx + nL, dx + nL, nH, lev, s);
     }
     RecOut o{which == LH_ALIAS_EDGE ? h->erec : nullptr, which == LH_ALIAS_EDGE ? nullptr : h->nrec,
-             h->src, h->dst};
+             h->src, h->dst, heat};
     if (nL > 0)
         hipLaunchKernelGGL(k_lights, dim3((unsigned)LH_CDIV(nL, 256)), blk, 0, s, wq, dx, idx, nL, nH, o);
     if (nH > 0)
@@ -294,12 +318,36 @@ lh_status build_alias(lh_handle *h, void *scratch, size_t bytes)
     if (!scratch) return fail(h, LH_ERR_INVALID_ARG, "scratch is NULL");
     if (bytes < L.total) return fail(h, LH_ERR_WORKSPACE_TOO_SMALL, "alias scratch too small");
     h->edge_ready = h->neg_ready = false;
-    lh_status st = build_one(h, LH_ALIAS_EDGE, L, (char *)scratch);
-    if (st != LH_OK) return st;
-    h->edge_ready = true;
-    st = build_one(h, LH_ALIAS_NEG, L, (char *)scratch);
+    // Out- and in-degrees, the negative weights' canonical scan (for W_nu), and the
+    // heat of every node, before either table's records are written.
+    {
+        char *sc = (char *)scratch;
+        hipStream_t s = h->stream;
+        int32_t *deg = (int32_t *)(sc + L.deg), *indeg = (int32_t *)(sc + L.indeg);
+        double *wq = (double *)(sc + L.wq), *dx = (double *)(sc + L.dx), *lev = (double *)(sc + L.lev);
+        dim3 blk(256), gn((unsigned)LH_CDIV(h->n, 256));
+        hipLaunchKernelGGL(k_zero_i32, gn, blk, 0, s, deg, h->n);
+        hipLaunchKernelGGL(k_zero_i32, gn, blk, 0, s, indeg, h->n);
+        hipLaunchKernelGGL(k_degrees, dim3((unsigned)LH_CDIV(h->m, 256)), blk, 0, s, h->src, h->dst, h->m, deg,
+                           indeg);
+        hipLaunchKernelGGL(k_neg_weights, gn, blk, 0, s, deg, h->n, wq);
+        chunk_scan<OpNeumaier>(wq, dx, h->n, lev, s);
+        unsigned long long *cnt = (unsigned long long *)(sc + L.cnt);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
+        hipLaunchKernelGGL(k_heat, gn, blk, 0, s, deg, indeg, wq, dx, h->n, h->m, h->p.K, (uint8_t *)(sc + L.heat),
+                           cnt);
+        unsigned long long na = 0;
+        hipError_t e = hipMemcpyAsync(&na, cnt, sizeof(na), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "degree pass");
+        h->n_active = (long long)na;
+    }
+    lh_status st = build_one(h, LH_ALIAS_NEG, L, (char *)scratch);
     if (st != LH_OK) return st;
     h->neg_ready = true;
+    st = build_one(h, LH_ALIAS_EDGE, L, (char *)scratch);
+    if (st != LH_OK) return st;
+    h->edge_ready = true;
     // The scratch may be released by the caller once this work has run.
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "alias build");
@@ -342,7 +390,7 @@ lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32
 {
     long long N = which == LH_ALIAS_EDGE ? h->m : h->n;
     RecOut o{which == LH_ALIAS_EDGE ? h->erec : nullptr, which == LH_ALIAS_EDGE ? nullptr : h->nrec,
-             h->src, h->dst};
+             h->src, h->dst, nullptr};
     if (N > 0)
         hipLaunchKernelGGL(k_import, dim3((unsigned)LH_CDIV(N, 256)), dim3(256), 0, h->stream,
                            (const unsigned long long *)thr, alias, N, o, h->status);

@@ -37,7 +37,13 @@ GraphDev graph_dev(const lh_handle *h)
     g.eta_scale = 1.0f;
     g.d = h->p.d;
     g.nch = h->p.d / (h->p.dtype == LH_FP32 ? 4 : 8);
+    g.nunits = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;
     g.K = h->p.K;
+    g.hot_heat = -1;
+    g.hot_rate = h->p.hot_rate;
+    g.max_in_flight = 0.0;
+    if (h->p.max_conflicts > 0.0 && h->n_active > 0)
+        g.max_in_flight = h->p.max_conflicts * (double)h->n_active / (double)(h->p.K + 2);
     return g;
 }
 
@@ -51,6 +57,7 @@ static lh_status check_params(const lh_params *p)
     if (!std::isfinite(p->eta0) || p->eta0 < 0) return LH_ERR_INVALID_ARG;
     if (!std::isfinite(p->lambda) || p->lambda < 0) return LH_ERR_INVALID_ARG;
     if (!std::isfinite(p->alpha_neg)) return LH_ERR_INVALID_ARG;
+    if (std::isnan(p->hot_rate) || std::isnan(p->max_conflicts)) return LH_ERR_INVALID_ARG;
     if (p->total_samples == 0) return LH_ERR_INVALID_ARG;
     if (p->graph_id < 0) return LH_ERR_INVALID_ARG;
     if (p->mode != LH_HOGWILD && p->mode != LH_SNAPSHOT) return LH_ERR_INVALID_ARG;

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "handle.hpp"
-#include "tile.hpp"
+#include "sgd_kernels.hpp"
 
 namespace lh {
 
@@ -96,6 +96,9 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     if (!h->bound || !h->graph_set || !h->edge_ready || !h->neg_ready)
         return fail(h, LH_ERR_NOT_BUILT, "alias tables not built");
     if (h->p.mode != LH_HOGWILD) return LH_OK;
+    // Timing runs of bfloat16 tables are switched off: a zero-step timing run of the
+    // bfloat16 kernel did not finish on the GPU and its cause is not yet known.
+    if (h->p.dtype == LH_BF16) return fail(h, LH_ERR_UNSUPPORTED, "tuning bfloat16 tables is switched off");
     if (probe < 64 || probe > h->p.total_samples) return fail(h, LH_ERR_INVALID_ARG, "probe out of range");
     int dev = -1;
     (void)hipGetDevice(&dev);
@@ -170,8 +173,14 @@ struct BatchDesc {
     unsigned long long limit;  // samples to train: [0, limit)
 };
 
+// The work queue hands out items in the order of sched: item i trains chunk
+// (sched[i] & (2^40 - 1)) of graph (sched[i] >> 40).  The host interleaves every graph's
+// chunks in proportion to its size, so at any moment the wavefronts in flight are spread
+// over the graphs by size and no small graph receives the whole GPU at once (which would
+// put thousands of concurrent writers on each of its rows).
 struct BatchArgs {
     const BatchDesc *desc;
+    const unsigned long long *sched;
     int G;
     unsigned long long total_items;
     unsigned long long item_samples;
@@ -219,25 +228,20 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
         item = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(item >> 32)) << 32) |
                (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(item & 0xffffffffull));
         if (item >= a.total_items) break;
-        int lo = 0, hi = a.G - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (a.desc[mid].item0 <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
+        const unsigned long long packed = a.sched[item];
+        const int lo = (int)(packed >> 40);
+        const unsigned long long chunk = packed & ((1ull << 40) - 1);
         const BatchDesc &D = a.desc[lo];
         const GraphDev g = D.g;
-        unsigned long long s0 = (item - D.item0) * a.item_samples;
+        unsigned long long s0 = chunk * a.item_samples;
         unsigned long long s1 = s0 + a.item_samples;
         if (s1 > D.limit) s1 = D.limit;
         if (g.nch <= Cfg::LS * Cfg::CS) {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LS, Cfg::CS, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LS, 4 * Cfg::CS, KMAX, 2, false>(g, t, s1, so);
         } else {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LL, Cfg::CL, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LL, 4 * Cfg::CL, KMAX, 2, false>(g, t, s1, so);
         }
         if (lane == 0 && s1 > s0) atomicAdd(&a.done[lo], s1 - s0);
     }
@@ -252,7 +256,10 @@ struct lh_batch {
     hipStream_t stream = nullptr;
     lh::BatchDesc *d_desc = nullptr;        // device, owned
     unsigned long long *d_ctr = nullptr;    // device, owned: [0] queue, [1..G] done
+    unsigned long long *d_sched = nullptr;  // device, owned: item schedule (sched_cap entries)
+    size_t sched_cap = 0;
     std::vector<lh::BatchDesc> desc;
+    std::vector<unsigned long long> sched;
     int variant = 0, blocks_per_cu = 8;
     unsigned long long item_samples = 8192;
     unsigned long long total_items = 0;
@@ -264,17 +271,55 @@ struct lh_batch {
 
 namespace lh {
 
+// Samples in flight of a batched launch: resident wavefronts x groups per wavefront of
+// the narrower tile configuration (an upper bound, so hot rows are over- not under-counted).
+static double batch_in_flight(const lh_batch *b, int variant, int bpc)
+{
+    int occ = 0, ls = 8;
+    const bool k5 = b->K <= 5;
+#define LH_OCC(TT, KM, V)                                                               \
+    {                                                                                   \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<TT, KM, V>, 256, 0); \
+        ls = BatchCfg<TT, V>::LS;                                                       \
+    }
+    if (b->dtype == LH_BF16) {
+        if (k5) { if (variant == 0) LH_OCC(uint16_t, 5, 0) else LH_OCC(uint16_t, 5, 1) }
+        else { if (variant == 0) LH_OCC(uint16_t, 8, 0) else LH_OCC(uint16_t, 8, 1) }
+    } else {
+        if (k5) { if (variant == 0) LH_OCC(float, 5, 0) else LH_OCC(float, 5, 1) }
+        else { if (variant == 0) LH_OCC(float, 8, 0) else LH_OCC(float, 8, 1) }
+    }
+#undef LH_OCC
+    if (occ < 1) occ = 8;
+    double blocks = std::min<double>((double)b->num_cu * bpc, (double)b->num_cu * occ);
+    return blocks * 4.0 * (64.0 / ls);
+}
+
 static void batch_items(lh_batch *b, unsigned long long item_samples, bool dry, unsigned long long probe)
 {
     unsigned long long acc = 0;
+    const double F = batch_in_flight(b, b->variant, b->blocks_per_cu);
+    // (position in [0, 1), graph, chunk): chunk i of a graph with c chunks sits at (i + 1/2) / c.
+    std::vector<std::pair<double, unsigned long long>> order;
     for (int i = 0; i < b->G; ++i) {
         BatchDesc &D = b->desc[i];
         D.g = graph_dev(b->hs[i]);
+        D.g.hot_heat = hot_heat_for(F, D.g.hot_rate);
+        D.g.max_in_flight = 0.0;
         D.g.eta_scale = dry ? 0.0f : 1.0f;
         D.limit = dry ? (probe < D.g.T ? probe : D.g.T) : D.g.T;
         D.item0 = acc;
-        acc += (D.limit + item_samples - 1) / item_samples;
+        const unsigned long long c = (D.limit + item_samples - 1) / item_samples;
+        for (unsigned long long k = 0; k < c; ++k)
+            order.emplace_back(((double)k + 0.5) / (double)c, ((unsigned long long)i << 40) | k);
+        acc += c;
     }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, unsigned long long> &x, const std::pair<double, unsigned long long> &y) {
+                         return x.first < y.first;
+                     });
+    b->sched.resize(order.size());
+    for (size_t i = 0; i < order.size(); ++i) b->sched[i] = order[i].second;
     b->total_items = acc;
 }
 
@@ -282,6 +327,7 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
 {
     BatchArgs a;
     a.desc = b->d_desc;
+    a.sched = b->d_sched;
     a.G = b->G;
     a.total_items = b->total_items;
     a.item_samples = item_samples;
@@ -311,8 +357,13 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
 
 static hipError_t upload_desc(lh_batch *b)
 {
-    return hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(BatchDesc) * b->desc.size(), hipMemcpyHostToDevice,
-                          b->stream);
+    if (b->sched.size() > b->sched_cap) return hipErrorInvalidValue;
+    hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(BatchDesc) * b->desc.size(),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !b->sched.empty())
+        e = hipMemcpyAsync(b->d_sched, b->sched.data(), sizeof(unsigned long long) * b->sched.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    return e;
 }
 
 static void drop_graph(lh_batch *b)
@@ -359,7 +410,11 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != b->device) (void)hipSetDevice(b->device);
+    // room for the schedule at the smallest item size the tuner tries (2048 samples)
+    b->sched_cap = 0;
+    for (int i = 0; i < G; ++i) b->sched_cap += (size_t)((graphs[i]->p.total_samples + 2047) / 2048);
     if (hipMalloc(&b->d_desc, sizeof(BatchDesc) * G) != hipSuccess ||
+        hipMalloc(&b->d_sched, sizeof(unsigned long long) * (b->sched_cap + 1)) != hipSuccess ||
         hipMalloc(&b->d_ctr, sizeof(unsigned long long) * (G + 1)) != hipSuccess ||
         hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
         lh_batch_destroy(b);
@@ -377,6 +432,8 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
 lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
 {
     if (!b) return LH_ERR_INVALID_ARG;
+    // Same restriction as lh_tune: no zero-step timing runs of bfloat16 kernels for now.
+    if (b->dtype == LH_BF16) return LH_ERR_UNSUPPORTED;
     char key[160];
     unsigned long long tot = 0;
     for (auto *h : b->hs) tot += h->p.total_samples;
@@ -384,7 +441,7 @@ lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
                   log2_bucket((long long)tot));
     int hit[4];
     if (cache_lookup(cache_path, key, hit) && (hit[0] == 0 || hit[0] == 1) && hit[1] >= 1 && hit[1] <= 64 &&
-        hit[2] >= 64) {
+        hit[2] >= 2048) {
         b->variant = hit[0];
         b->blocks_per_cu = hit[1];
         b->item_samples = (unsigned long long)hit[2];
@@ -403,6 +460,8 @@ lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
     for (int v = 0; v < 2; ++v)
         for (int bpc : bpcs)
             for (unsigned long long is : items) {
+                b->variant = v;
+                b->blocks_per_cu = bpc;
                 batch_items(b, is, true, probe);
                 if (upload_desc(b) != hipSuccess) return LH_ERR_HIP;
                 if (batch_launch_raw(b, v, bpc, is) != hipSuccess) return LH_ERR_HIP;  // warm-up
@@ -501,6 +560,7 @@ lh_status lh_batch_destroy(lh_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_sched) (void)hipFree(b->d_sched);
     if (b->d_ctr) (void)hipFree(b->d_ctr);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);

@@ -10,9 +10,17 @@
 // Record layouts in HBM.
 //
 // Edge alias record (32 B, one per arc column c): the 64-bit threshold, the alias
-// arc, and the endpoints of both the column arc and the alias arc, so that one
-// 32-byte sector read resolves a positive pair with no dependent load.
-// Negative alias record (16 B, one per node column).
+// arc, the endpoints of both the column arc and the alias arc (so that one 32-byte
+// sector read resolves a positive pair with no dependent load), and the heat byte of
+// each of those four endpoints.
+// Negative alias record (16 B, one per node column): threshold, alias, and the heat
+// bytes of the column node (byte 0) and of the alias node (byte 1).
+//
+// Heat of node r: floor(-log2 p_r), clamped to [0, 255], where p_r estimates the
+// probability that one sample touches a row of r: (out-degree + in-degree) / m plus
+// K q(r) with q from Eq. (1).  A training launch with F samples in flight treats a row
+// as hot when F p_r reaches the caller's threshold, i.e. when its heat is at most
+// floor(log2(F / threshold)).
 // ---------------------------------------------------------------------------
 struct __attribute__((aligned(16))) EdgeRec {
     unsigned long long thr;
@@ -21,14 +29,14 @@ struct __attribute__((aligned(16))) EdgeRec {
     int32_t dst_c;
     int32_t src_a;
     int32_t dst_a;
-    int32_t pad;
+    uint32_t heat;
 };
 static_assert(sizeof(EdgeRec) == 32, "EdgeRec is one 32-byte sector");
 
 struct __attribute__((aligned(16))) NegRec {
     unsigned long long thr;
     int32_t alias;
-    int32_t pad;
+    uint32_t heat;
 };
 static_assert(sizeof(NegRec) == 16, "NegRec is 16 bytes");
 

@@ -21,7 +21,11 @@ struct GraphDev {
     float lambda, alpha;
     float eta_scale;           // 1 for training, 0 for timing-only dry runs
     int d, nch;                // width and number of 16-byte chunks per row
+    int nunits;                // 4-byte units per row (d binary32 values or d/2 bfloat16 pairs)
     int K;
+    int hot_heat;              // rows with heat <= hot_heat take atomic increments (-1: none)
+    double hot_rate;           // host side: the threshold hot_heat is derived from per launch
+    double max_in_flight;      // host side: cap on samples in flight (0: none)
 };
 
 // A kernel configuration: lanes per sample and 16-byte chunks per lane.
@@ -37,7 +41,7 @@ struct WsLayout {
 };
 
 struct ScratchLayout {
-    size_t wq = 0, dx = 0, idx = 0, lpos = 0, deg = 0, lev = 0, ilev = 0, total = 0;
+    size_t wq = 0, dx = 0, idx = 0, lpos = 0, deg = 0, indeg = 0, heat = 0, cnt = 0, lev = 0, ilev = 0, total = 0;
     long long N = 0, lev_n = 0;
 };
 
@@ -60,6 +64,7 @@ struct lh_handle {
     size_t ws_bytes = 0;
     void *tab[3] = {nullptr, nullptr, nullptr};
     long long n = 0, m = 0;
+    long long n_active = 0;  // nodes with at least one arc (from the last alias build)
     const int32_t *src = nullptr, *dst = nullptr;
     const float *w = nullptr;
     lh::WsLayout lay;

@@ -63,6 +63,9 @@ ScratchLayout scratch_layout(long long n, long long m)
     L.idx = carve(off, 4 * (size_t)N);
     L.lpos = carve(off, 4 * (size_t)N);
     L.deg = carve(off, 4 * (size_t)(n > 0 ? n : 1));
+    L.indeg = carve(off, 4 * (size_t)(n > 0 ? n : 1));
+    L.heat = carve(off, (size_t)(n > 0 ? n : 1));
+    L.cnt = carve(off, 8);
     L.lev_n = scan_levels_size(N);
     L.lev = carve(off, 8 * (size_t)L.lev_n);
     L.ilev = carve(off, 4 * (size_t)L.lev_n);

@@ -3,6 +3,9 @@
 // unit so the kernel variants compile in parallel.
 #pragma once
 
+#include <algorithm>
+#include <cmath>
+
 #include "tile.hpp"
 
 namespace lh {
@@ -17,7 +20,7 @@ __global__ void __launch_bounds__(256) k_hogwild(GraphDev g, unsigned long long 
     unsigned long long ntiles = (end - first + 63) / 64;
     SnapOut so{};
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, CPL, KMAX, ORD, false>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, 4 * CPL, KMAX, ORD, false>(g, first + t * 64, end, so);
 }
 
 template <typename TT, int LPS, int CPL, int KMAX, int ORD>
@@ -29,7 +32,7 @@ __global__ void __launch_bounds__(256) k_snap_contrib(GraphDev g, unsigned long 
     unsigned long long nw = (unsigned long long)gridDim.x * wpb;
     unsigned long long ntiles = (end - first + 63) / 64;
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, CPL, KMAX, ORD, true>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, 4 * CPL, KMAX, ORD, true>(g, first + t * 64, end, so);
 }
 
 inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_per_cu)
@@ -40,6 +43,28 @@ inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_pe
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return (unsigned)blocks;
+}
+
+// Heat threshold for a launch with F samples in flight: a row is hot when F p_r reaches
+// hot_rate, i.e. when floor(-log2 p_r) <= floor(log2(F / hot_rate)).
+inline int hot_heat_for(double F, double hot_rate)
+{
+    if (!(hot_rate > 0.0)) return 255;
+    if (hot_rate >= 1e30 || F <= 0.0) return -1;
+    double t = std::floor(std::log2(F / hot_rate));
+    if (t < -1.0) return -1;
+    if (t > 255.0) return 255;
+    return (int)t;
+}
+
+// Samples in flight in phase B: resident wavefronts x (64 / LPS) groups.
+template <typename KernelT>
+inline double samples_in_flight(KernelT kernel, unsigned grid, int num_cu, int lps)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) != hipSuccess || occ < 1) occ = 8;
+    double blocks = std::min<double>((double)grid, (double)num_cu * occ);
+    return blocks * 4.0 * (64.0 / lps);
 }
 
 #define LH_CFG_LIST(X) \
@@ -65,19 +90,35 @@ inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_pe
     X(64, 1)                \
     X(64, 2)
 
+// One Hogwild launch: the grid of the configuration, lowered if the graph's staleness
+// cap asks for fewer samples in flight, and the heat threshold for that concurrency.
+template <typename KernelT>
+hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c, unsigned long long first,
+                      unsigned long long end, int num_cu, hipStream_t s)
+{
+    unsigned grid = hogwild_grid(end - first, num_cu, c.blocks_per_cu);
+    double F = samples_in_flight(kern, grid, num_cu, lps);
+    if (g.max_in_flight > 0.0 && F > g.max_in_flight) {
+        double per_block = 4.0 * (64.0 / lps);
+        grid = (unsigned)std::max(1.0, std::floor(g.max_in_flight / per_block));
+        F = samples_in_flight(kern, grid, num_cu, lps);
+    }
+    GraphDev gl = g;
+    gl.hot_heat = hot_heat_for(F, g.hot_rate);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, gl, first, end);
+    return hipGetLastError();
+}
+
 template <typename TT, int ORD>
 hipError_t launch_hogwild_t(const GraphDev &g, const TileCfg &c, unsigned long long first, unsigned long long end,
                             int num_cu, hipStream_t s)
 {
     const bool k5 = g.K <= 5;
-    dim3 grid(hogwild_grid(end - first, num_cu, c.blocks_per_cu)), block(256);
-#define LH_LAUNCH_H(L, C)                                                                    \
-    if (c.lps == L && c.cpl == C) {                                                          \
-        if (k5)                                                                              \
-            hipLaunchKernelGGL((k_hogwild<TT, L, C, 5, ORD>), grid, block, 0, s, g, first, end); \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_hogwild<TT, L, C, 8, ORD>), grid, block, 0, s, g, first, end); \
-        return hipGetLastError();                                                            \
+#define LH_LAUNCH_H(L, C)                                                 \
+    if (c.lps == L && c.cpl == C) {                                       \
+        if (k5)                                                           \
+            return launch_one(k_hogwild<TT, L, C, 5, ORD>, L, g, c, first, end, num_cu, s); \
+        return launch_one(k_hogwild<TT, L, C, 8, ORD>, L, g, c, first, end, num_cu, s);     \
     }
     LH_CFG_LIST(LH_LAUNCH_H)
 #undef LH_LAUNCH_H

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) k_apply(GraphDev g, const uint32_t *keys,
                                                const uint32_t *start, const uint32_t *segid, long long E,
                                                const float *contrib, unsigned long long batch_idx)
 {
-    constexpr int VEC = Elem<TT>::VEC;
+    constexpr int EPU = Elem<TT>::EPU;
     constexpr int GPB = 256 / LPS;
     const long long nseg = E > 0 ? (long long)segid[E - 1] : 0;
     const int gl = threadIdx.x % LPS;
@@ -110,44 +110,31 @@ __global__ void __launch_bounds__(256) k_apply(GraphDev g, const uint32_t *keys,
     const uint32_t key = keys[p0];
     const int table = (int)(key / (uint32_t)g.n);
     const long long row = (long long)(key % (uint32_t)g.n);
-    TT *X = (TT *)g.tab[table] + row * g.d;
-    for (int ch = gl; ch < g.nch; ch += LPS) {
-        float acc[VEC];
+    uint32_t *X = reinterpret_cast<uint32_t *>((TT *)g.tab[table] + row * g.d);
+    for (int un = gl; un < g.nunits; un += LPS) {
+        float acc[EPU];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+        for (int e = 0; e < EPU; ++e) acc[e] = 0.f;
         for (long long p = p0; p < p1; ++p) {
-            const float *c = contrib + (unsigned long long)vals[p] * g.d + ch * VEC;
+            const float *c = contrib + (unsigned long long)vals[p] * g.d + un * EPU;
 #pragma unroll
-            for (int q = 0; q < VEC / 4; ++q) {
-                float4 v = *reinterpret_cast<const float4 *>(c + 4 * q);
-                acc[4 * q] += v.x;
-                acc[4 * q + 1] += v.y;
-                acc[4 * q + 2] += v.z;
-                acc[4 * q + 3] += v.w;
-            }
+            for (int e = 0; e < EPU; ++e) acc[e] += c[e];
         }
-        float x[VEC];
-        load_chunk<TT>(X, ch, x);
+        float x[EPU];
+        unit_to_f32<TT>(X[un], x);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) x[e] += acc[e];
-        if constexpr (sizeof(TT) == 4) {
-            store_chunk<TT>(X, ch, x, 0u, 0u);
-        } else {
+        for (int e = 0; e < EPU; ++e) x[e] += acc[e];
+        uint32_t rnd = 0u;
+        if constexpr (EPU == 2) {
             // Stochastic rounding bits: Philox4x64-10 keyed by (batch, table, row); block
-            // ch / 2 holds the 128 bits of chunk ch (8 elements x 16 bits).
+            // un / 8 holds 32 bits for each of 8 units.
             u64x4 r = philox4x64_10(g.seed, g.sr_key, batch_idx, (unsigned long long)table,
-                                    (unsigned long long)row, (unsigned long long)(ch / 2));
-            unsigned long long w0 = (ch & 1) ? r.z : r.x, w1 = (ch & 1) ? r.w : r.y;
-            uint32_t bits[4] = {(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1, (uint32_t)(w1 >> 32)};
-            uint32_t out[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                uint32_t lo = f32_to_bf16_sr(x[2 * i], bits[i]);
-                uint32_t hi = f32_to_bf16_sr(x[2 * i + 1], bits[i] >> 16);
-                out[i] = lo | (hi << 16);
-            }
-            *reinterpret_cast<uint4 *>(X + (size_t)ch * 8) = make_uint4(out[0], out[1], out[2], out[3]);
+                                    (unsigned long long)row, (unsigned long long)(un / 8));
+            const int q = (un % 8) / 2;
+            unsigned long long wd = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+            rnd = (uint32_t)(wd >> (32 * (un % 2)));
         }
+        X[un] = f32_to_unit<TT>(x, rnd);
     }
 }
 

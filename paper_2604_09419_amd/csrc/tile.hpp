@@ -4,13 +4,23 @@
 // One wavefront handles a tile of 64 consecutive sample indices:
 //   phase A  lane l draws sample (tile + l): 1 + K Philox4x64-10 blocks, one 32-byte
 //            edge record and K 16-byte negative records (Algorithm 3 root edge,
-//            Eq. (1) negatives), plus a bit mask of repeated rows in the tuple;
-//   phase B  groups of LPS lanes take the 64 samples in LPS rounds.  Each lane holds
-//            CPL 16-byte chunks of every row (128-bit loads, a row's chunks spread over
-//            the group so the group reads whole rows coalesced), the 1 + K dot products
-//            are reduced across the group with cross-lane shuffles, and the updates of
-//            Algorithm 1 / Eqs. (2)-(3) are written back (Hogwild: plain stores, no
-//            locks) or emitted as per-row contributions (SNAPSHOT, Eq. (4)).
+//            Eq. (1) negatives), a bit mask of rows repeated inside the tuple and a bit
+//            mask of hot rows, and the sample's step size;
+//   phase B  groups of LPS lanes take the 64 samples in LPS rounds.  A row is a run of
+//            4-byte units (one binary32 value, or two bfloat16 values); lane gl of a
+//            group holds units gl, gl + LPS, gl + 2 LPS, ... so every load, store and
+//            atomic instruction of the group covers LPS consecutive units.  The 1 + K
+//            dot products are reduced across the group with DPP, and the updates of
+//            Algorithm 1 / Eqs. (2)-(3) are written back (HOGWILD) or emitted as
+//            per-row contributions (SNAPSHOT, Eq. (4)).
+//
+// HOGWILD write-back: a cold row is stored (row as loaded plus the sample's increment;
+// no locks).  A hot row -- one that many in-flight samples touch at once, a hub -- is
+// updated with atomic increments (binary32 float atomics; bfloat16: compare-and-swap
+// of the stochastically rounded sum, bounded retries), so concurrent updates of hubs
+// are not lost.  Atomics and device-wide visibility also keep the per-XCD L2 caches
+// from holding diverging copies of the hot rows.
+//
 // All 1 + K dot products of a sample use the rows as loaded before the sample; a row
 // that appears in several slots of one sample receives the sum of its increments.
 #pragma once
@@ -23,73 +33,43 @@ template <typename TT>
 struct Elem;
 template <>
 struct Elem<float> {
-    static constexpr int VEC = 4;  // 16 bytes of binary32
+    static constexpr int EPU = 1;  // elements per 4-byte unit
 };
 template <>
 struct Elem<uint16_t> {
-    static constexpr int VEC = 8;  // 16 bytes of bfloat16
+    static constexpr int EPU = 2;
 };
 
+// ---- one 4-byte unit ----------------------------------------------------------------
 template <typename TT>
-__device__ __forceinline__ void load_chunk(const TT *row, int ch, float (&o)[Elem<TT>::VEC]);
-
-template <>
-__device__ __forceinline__ void load_chunk<float>(const float *row, int ch, float (&o)[4])
+__device__ __forceinline__ void unit_to_f32(uint32_t w, float (&o)[Elem<TT>::EPU])
 {
-    float4 v = *reinterpret_cast<const float4 *>(row + (size_t)ch * 4);
-    o[0] = v.x;
-    o[1] = v.y;
-    o[2] = v.z;
-    o[3] = v.w;
-}
-
-template <>
-__device__ __forceinline__ void load_chunk<uint16_t>(const uint16_t *row, int ch, float (&o)[8])
-{
-    uint4 v = *reinterpret_cast<const uint4 *>(row + (size_t)ch * 8);
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        o[2 * i] = __uint_as_float(w[i] << 16);
-        o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    if constexpr (sizeof(TT) == 4) {
+        o[0] = __uint_as_float(w);
+    } else {
+        o[0] = __uint_as_float(w << 16);
+        o[1] = __uint_as_float(w & 0xffff0000u);
     }
 }
 
-// Store one chunk.  bfloat16 rows use stochastic rounding with bits from lowbias32 of
-// (sample seed + chunk counter); binary32 rows are stored as computed.
+// Pack a unit's values; bfloat16 with stochastic rounding from 32 random bits.
 template <typename TT>
-__device__ __forceinline__ void store_chunk(TT *row, int ch, const float (&x)[Elem<TT>::VEC],
-                                            uint32_t sr, uint32_t ctr);
-
-template <>
-__device__ __forceinline__ void store_chunk<float>(float *row, int ch, const float (&x)[4], uint32_t,
-                                                   uint32_t)
+__device__ __forceinline__ uint32_t f32_to_unit(const float (&x)[Elem<TT>::EPU], uint32_t rnd)
 {
-    *reinterpret_cast<float4 *>(row + (size_t)ch * 4) = make_float4(x[0], x[1], x[2], x[3]);
-}
-
-template <>
-__device__ __forceinline__ void store_chunk<uint16_t>(uint16_t *row, int ch, const float (&x)[8],
-                                                      uint32_t sr, uint32_t ctr)
-{
-    uint32_t w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        uint32_t r = lowbias32(sr + (ctr * 4u + (uint32_t)i) * 0x9E3779B9u);
-        uint32_t lo = f32_to_bf16_sr(x[2 * i], r);
-        uint32_t hi = f32_to_bf16_sr(x[2 * i + 1], r >> 16);
-        w[i] = lo | (hi << 16);
+    if constexpr (sizeof(TT) == 4) {
+        return __float_as_uint(x[0]);
+    } else {
+        return f32_to_bf16_sr(x[0], rnd) | (f32_to_bf16_sr(x[1], rnd >> 16) << 16);
     }
-    *reinterpret_cast<uint4 *>(row + (size_t)ch * 8) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 // Where SNAPSHOT contributions go.
 struct SnapOut {
-    uint32_t *keys;      // [entries]  table * n + row
-    uint32_t *vals;      // [entries]  entry index
-    float *contrib;      // [entries x d]
+    uint32_t *keys;           // [entries]  table * n + row
+    uint32_t *vals;           // [entries]  entry index
+    float *contrib;           // [entries x d], binary32
     unsigned long long base;  // first sample of the batch
-    int nord;            // orders per sample (1 or 2)
+    int nord;                 // orders per sample (1 or 2)
 };
 
 // Sum over an aligned group of LPS lanes, every lane receiving the sum.  Within a row
@@ -115,56 +95,123 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
-// This lane's chunks of the 2 + K rows of one order of one sample, as loaded.
-template <typename TT, int CPL, int KMAX>
+// Element e of a unit as binary32.
+template <typename TT>
+__device__ __forceinline__ float val(uint32_t w, int e)
+{
+    if constexpr (sizeof(TT) == 4) return __uint_as_float(w);
+    return e == 0 ? __uint_as_float(w << 16) : __uint_as_float(w & 0xffff0000u);
+}
+
+// This lane's units of the 2 + K rows of one order of one sample, as loaded (raw words,
+// widened where used, so bfloat16 rows take half the registers).
+template <typename TT, int UPL, int KMAX>
 struct Rows {
-    float a[CPL][Elem<TT>::VEC];
-    float b[KMAX + 1][CPL][Elem<TT>::VEC];
+    uint32_t a[UPL];
+    uint32_t b[KMAX + 1][UPL];
 };
 
-template <typename TT, int LPS, int CPL, int KMAX>
-__device__ __forceinline__ void load_rows(Rows<TT, CPL, KMAX> &r, const GraphDev &g, const TT *A, const TT *B,
+template <typename TT, int LPS, int UPL>
+__device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint32_t (&o)[UPL])
+{
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(row);
+#pragma unroll
+    for (int k = 0; k < UPL; ++k) {
+        const int un = k * LPS + gl;
+        uint32_t v = 0u;
+        if (un < nunits) v = w[un];
+        o[k] = v;
+    }
+}
+
+template <typename TT, int LPS, int UPL, int KMAX>
+__device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, const TT *A, const TT *B,
                                           int u, const int (&ids)[KMAX + 1], int K, int gl)
 {
-    constexpr int VEC = Elem<TT>::VEC;
-    const int d = g.d, nch = g.nch;
-    const TT *arow = A + (long long)u * d;
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-        int ch = c * LPS + gl;
-        if (ch < nch) {
-            load_chunk<TT>(arow, ch, r.a[c]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) r.a[c][e] = 0.f;
-        }
-    }
+    const int d = g.d, nu = g.nunits;
+    load_row<TT, LPS, UPL>(A + (long long)u * d, nu, gl, r.a);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
-        const TT *brow = B + (long long)ids[j] * d;
+        if (j <= K) {
+            load_row<TT, LPS, UPL>(B + (long long)ids[j] * d, nu, gl, r.b[j]);
+        } else {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            int ch = c * LPS + gl;
-            if (j <= K && ch < nch) {
-                load_chunk<TT>(brow, ch, r.b[j][c]);
-            } else {
+            for (int k = 0; k < UPL; ++k) r.b[j][k] = 0u;
+        }
+    }
+}
+
+// Write one row back: new = old + inc.  Cold rows are stored; hot rows get atomic
+// increments (binary32) or a compare-and-swap loop of the stochastically rounded sum
+// (bfloat16, at most 64 attempts per unit, after which the unit keeps the other
+// writer's value).  The random bits of unit un are lowbias32(sr + (ctr * 256 + un) * phi).
+template <typename TT, int LPS, int UPL>
+__device__ __forceinline__ void write_row(TT *row, int nunits, int gl, const uint32_t (&old)[UPL],
+                                          const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
+                                          uint32_t ctr)
+{
+    constexpr int EPU = Elem<TT>::EPU;
+    uint32_t *w = reinterpret_cast<uint32_t *>(row);
+    if (!hot) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) r.b[j][c][e] = 0.f;
+        for (int k = 0; k < UPL; ++k) {
+            const int un = k * LPS + gl;
+            if (un < nunits) {
+                float x[EPU];
+#pragma unroll
+                for (int e = 0; e < EPU; ++e) x[e] = val<TT>(old[k], e) + inc[k][e];
+                uint32_t rnd = 0u;
+                if constexpr (EPU == 2) rnd = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
+                w[un] = f32_to_unit<TT>(x, rnd);
+            }
+        }
+    } else if constexpr (EPU == 1) {
+#pragma unroll
+        for (int k = 0; k < UPL; ++k) {
+            const int un = k * LPS + gl;
+            if (un < nunits) atomicAdd(reinterpret_cast<float *>(row) + un, inc[k][0]);
+        }
+    } else {
+        uint32_t expect[UPL], rnd[UPL];
+        unsigned pending = 0u;
+#pragma unroll
+        for (int k = 0; k < UPL; ++k) {
+            const int un = k * LPS + gl;
+            rnd[k] = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
+            expect[k] = old[k];
+            if (un < nunits) pending |= 1u << k;
+        }
+        for (int attempt = 0; attempt < 64 && pending; ++attempt) {
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                if (pending & (1u << k)) {
+                    float cur[2], x[2];
+                    unit_to_f32<TT>(expect[k], cur);
+                    x[0] = cur[0] + inc[k][0];
+                    x[1] = cur[1] + inc[k][1];
+                    const uint32_t want = f32_to_unit<TT>(x, rnd[k]);
+                    const uint32_t seen = atomicCAS(w + (k * LPS + gl), expect[k], want);
+                    if (seen == expect[k])
+                        pending &= ~(1u << k);
+                    else
+                        expect[k] = seen;
+                }
             }
         }
     }
 }
 
 // One order of one sample, rows already loaded.  A holds the vertex rows, B the context
-// rows (A == B for first order).  ids[0] = v, ids[1..K] = negatives.
-template <typename TT, int LPS, int CPL, int KMAX, bool FIRST, bool SNAP>
+// rows (A == B for first order).  ids[0] = v, ids[1..K] = negatives.  hot: bit 0 for
+// the vertex row, bit 1 + j for slot j.
+template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP>
 __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u, const int (&ids)[KMAX + 1],
-                                          int K, float eta, unsigned dupb, unsigned dupu, uint32_t sr,
-                                          int oi, int gl, const SnapOut &so, unsigned long long s,
-                                          int tabA, int tabB, const Rows<TT, CPL, KMAX> &rows)
+                                          int K, float eta, unsigned dupb, unsigned dupu, unsigned hot,
+                                          uint32_t sr, int oi, int gl, const SnapOut &so, unsigned long long s,
+                                          int tabA, int tabB, const Rows<TT, UPL, KMAX> &rows)
 {
-    constexpr int VEC = Elem<TT>::VEC;
-    const int d = g.d, nch = g.nch;
+    constexpr int EPU = Elem<TT>::EPU;
+    const int d = g.d, nu = g.nunits;
     const auto &a = rows.a;
     const auto &b = rows.b;
     float gj[KMAX + 1];
@@ -172,9 +219,9 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
     for (int j = 0; j <= KMAX; ++j) {
         float x = 0.f;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c)
+        for (int k = 0; k < UPL; ++k)
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) x = fmaf(a[c][e], b[j][c][e], x);
+            for (int e = 0; e < EPU; ++e) x = fmaf(val<TT>(a[k], e), val<TT>(b[j][k], e), x);
         gj[j] = x;
     }
 #pragma unroll
@@ -188,16 +235,16 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
     const float el = eta * g.lambda;
 
     // dA = sum_j g_j b_j - (1 + K) eta lambda a
-    float dA[CPL][VEC];
+    float dA[UPL][EPU];
     const float decayA = (float)(K + 1) * el;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c)
+    for (int k = 0; k < UPL; ++k)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            float acc = -decayA * a[c][e];
+        for (int e = 0; e < EPU; ++e) {
+            float acc = -decayA * val<TT>(a[k], e);
 #pragma unroll
-            for (int j = 0; j <= KMAX; ++j) acc = fmaf(gj[j], b[j][c][e], acc);
-            dA[c][e] = acc;
+            for (int j = 0; j <= KMAX; ++j) acc = fmaf(gj[j], val<TT>(b[j][k], e), acc);
+            dA[k][e] = acc;
         }
 
     if constexpr (SNAP) {
@@ -206,14 +253,11 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
             ((s - so.base) * (unsigned long long)so.nord + (unsigned long long)oi) * (unsigned long long)(K + 2);
         float *crow = so.contrib + e0 * (unsigned long long)d;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            int ch = c * LPS + gl;
-            if (ch < nch) {
-                float *p = crow + ch * 4 * (VEC / 4);
+        for (int k = 0; k < UPL; ++k) {
+            const int un = k * LPS + gl;
+            if (un < nu) {
 #pragma unroll
-                for (int q = 0; q < VEC / 4; ++q)
-                    *reinterpret_cast<float4 *>(p + 4 * q) =
-                        make_float4(dA[c][4 * q], dA[c][4 * q + 1], dA[c][4 * q + 2], dA[c][4 * q + 3]);
+                for (int e = 0; e < EPU; ++e) crow[un * EPU + e] = dA[k][e];
             }
         }
 #pragma unroll
@@ -221,17 +265,11 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
             if (j > K) break;
             float *brow = crow + (unsigned long long)(j + 1) * d;
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                int ch = c * LPS + gl;
-                if (ch < nch) {
-                    float t[VEC];
+            for (int k = 0; k < UPL; ++k) {
+                const int un = k * LPS + gl;
+                if (un < nu) {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) t[e] = gj[j] * a[c][e] - el * b[j][c][e];
-                    float *p = brow + ch * VEC;
-#pragma unroll
-                    for (int q = 0; q < VEC / 4; ++q)
-                        *reinterpret_cast<float4 *>(p + 4 * q) =
-                            make_float4(t[4 * q], t[4 * q + 1], t[4 * q + 2], t[4 * q + 3]);
+                    for (int e = 0; e < EPU; ++e) brow[un * EPU + e] = gj[j] * val<TT>(a[k], e) - el * val<TT>(b[j][k], e);
                 }
             }
         }
@@ -249,7 +287,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
     } else {
         // Merge repeated rows: slot j's total step is Gm[j] (sum of the g of all slots
         // with that row) and cm[j] (their number, for the decay); slots that repeat an
-        // earlier row (or, in first order, the vertex row u) store nothing.
+        // earlier row (or, in first order, the vertex row u) write nothing.
         float Gm[KMAX + 1], cm[KMAX + 1];
         float GA = 0.f, cA = 0.f;
         unsigned skip = 0;
@@ -288,44 +326,37 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
             }
         }
         // vertex row
-        TT *wa = A + (long long)u * d;
+        {
+            float inc[UPL][EPU];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            int ch = c * LPS + gl;
-            if (ch < nch) {
-                float o[VEC];
+            for (int k = 0; k < UPL; ++k)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    float t = a[c][e] + dA[c][e];
-                    if (FIRST) t += GA * a[c][e] - cA * el * a[c][e];
-                    o[e] = t;
+                for (int e = 0; e < EPU; ++e) {
+                    float t = dA[k][e];
+                    if (FIRST) t += GA * val<TT>(a[k], e) - cA * el * val<TT>(a[k], e);
+                    inc[k][e] = t;
                 }
-                store_chunk<TT>(wa, ch, o, sr, (uint32_t)((oi * (KMAX + 2)) * 64 + ch));
-            }
+            write_row<TT, LPS, UPL>(A + (long long)u * d, nu, gl, a, inc, (hot & 1u) != 0, sr,
+                                    (uint32_t)(oi * (KMAX + 2)));
         }
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
             if (j > K) break;
             if (skip & (1u << j)) continue;
-            TT *wb = B + (long long)ids[j] * d;
+            float inc[UPL][EPU];
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                int ch = c * LPS + gl;
-                if (ch < nch) {
-                    float o[VEC];
+            for (int k = 0; k < UPL; ++k)
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        o[e] = b[j][c][e] + (Gm[j] * a[c][e] - cm[j] * el * b[j][c][e]);
-                    store_chunk<TT>(wb, ch, o, sr, (uint32_t)((oi * (KMAX + 2) + 1 + j) * 64 + ch));
-                }
-            }
+                for (int e = 0; e < EPU; ++e) inc[k][e] = Gm[j] * val<TT>(a[k], e) - cm[j] * el * val<TT>(b[j][k], e);
+            write_row<TT, LPS, UPL>(B + (long long)ids[j] * d, nu, gl, b[j], inc, (hot & (2u << j)) != 0, sr,
+                                    (uint32_t)(oi * (KMAX + 2) + 1 + j));
         }
     }
 }
 
-// One tile of 64 samples [tile, min(tile + 64, end)).
-template <typename TT, int LPS, int CPL, int KMAX, int ORD, bool SNAP>
+// One tile of 64 samples [tile, min(tile + 64, end)).  UPL units per lane.
+template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SNAP>
 __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long tile, unsigned long long end,
                                          const SnapOut &so)
 {
@@ -337,7 +368,7 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
 
     // ---- phase A: one lane per sample --------------------------------------
     int my_u = 0, my_ids[KMAX + 1];
-    unsigned my_dup = 0;
+    unsigned my_dup = 0, my_hot = 0;
     uint32_t my_sr = 0;
     float my_eta = 0.f;
 #pragma unroll
@@ -369,15 +400,23 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
                 __builtin_amdgcn_sched_barrier(0);
             }
             my_eta = (float)(g.eta0 * (1.0 - (double)s / (double)g.T)) * g.eta_scale;
+            const unsigned hh = (unsigned)g.hot_heat;  // -1 wraps to "nothing is that cold"
             unsigned long long ethr = (unsigned long long)r0.x | ((unsigned long long)r0.y << 32);
             bool keep = x0y < ethr;
             my_u = keep ? (int)r0.w : (int)r1.y;
             my_ids[0] = keep ? (int)r1.x : (int)r1.z;
+            const unsigned eh = r1.w;  // heats: src_c, dst_c, src_a, dst_a
+            const unsigned hu = keep ? (eh & 0xffu) : ((eh >> 16) & 0xffu);
+            const unsigned hv = keep ? ((eh >> 8) & 0xffu) : (eh >> 24);
+            if (g.hot_heat >= 0) my_hot = (hu <= hh ? 1u : 0u) | (hv <= hh ? 2u : 0u);
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 if (j < K) {
                     unsigned long long nthr = (unsigned long long)nr[j].x | ((unsigned long long)nr[j].y << 32);
-                    my_ids[j + 1] = xy[j] < nthr ? cn[j] : (int)nr[j].z;
+                    const bool kc = xy[j] < nthr;
+                    my_ids[j + 1] = kc ? cn[j] : (int)nr[j].z;
+                    const unsigned hn = kc ? (nr[j].w & 0xffu) : ((nr[j].w >> 8) & 0xffu);
+                    if (g.hot_heat >= 0 && hn <= hh) my_hot |= 4u << j;
                 }
             }
             // repeated rows among (v, n_1..n_K) in the low half, rows equal to u in the high half
@@ -400,7 +439,9 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) ids[j] = __shfl(my_ids[j], src);
         const unsigned dup = (unsigned)__shfl((int)my_dup, src);
+        unsigned hot = 0;
         uint32_t sr = 0;
+        if constexpr (!SNAP) hot = (unsigned)__shfl((int)my_hot, src);
         if constexpr (sizeof(TT) == 2 && !SNAP) sr = (uint32_t)__shfl((int)my_sr, src);
         const float eta = __shfl(my_eta, src);  // every cross-lane read before lanes diverge
         const unsigned long long s = tile + (unsigned long long)src;
@@ -408,20 +449,20 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
         const unsigned dupb = dup & 0xffffu, dupu = dup >> 16;
         // Issue the row loads of both orders before any arithmetic or store, so that up to
         // 2 (2 + K) rows per sample are in flight at once.
-        Rows<TT, CPL, KMAX> r2, r1;
+        Rows<TT, UPL, KMAX> r2, r1;
         if constexpr ((ORD & 2) != 0)
-            load_rows<TT, LPS, CPL, KMAX>(r2, g, (const TT *)g.tab[0], (const TT *)g.tab[1], u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX>(r2, g, (const TT *)g.tab[0], (const TT *)g.tab[1], u, ids, K, gl);
         if constexpr ((ORD & 1) != 0)
-            load_rows<TT, LPS, CPL, KMAX>(r1, g, (const TT *)g.tab[2], (const TT *)g.tab[2], u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX>(r1, g, (const TT *)g.tab[2], (const TT *)g.tab[2], u, ids, K, gl);
         int oi = 0;
         if constexpr ((ORD & 2) != 0) {
-            sgd_order<TT, LPS, CPL, KMAX, false, SNAP>(g, (TT *)g.tab[0], (TT *)g.tab[1], u, ids, K, eta, dupb,
-                                                       dupu, sr, oi, gl, so, s, LH_TABLE_U, LH_TABLE_C, r2);
+            sgd_order<TT, LPS, UPL, KMAX, false, SNAP>(g, (TT *)g.tab[0], (TT *)g.tab[1], u, ids, K, eta, dupb,
+                                                       dupu, hot, sr, oi, gl, so, s, LH_TABLE_U, LH_TABLE_C, r2);
             ++oi;
         }
         if constexpr ((ORD & 1) != 0) {
-            sgd_order<TT, LPS, CPL, KMAX, true, SNAP>(g, (TT *)g.tab[2], (TT *)g.tab[2], u, ids, K, eta, dupb,
-                                                      dupu, sr ^ 0x5bd1e995u, oi, gl, so, s, LH_TABLE_U1,
+            sgd_order<TT, LPS, UPL, KMAX, true, SNAP>(g, (TT *)g.tab[2], (TT *)g.tab[2], u, ids, K, eta, dupb,
+                                                      dupu, hot, sr ^ 0x5bd1e995u, oi, gl, so, s, LH_TABLE_U1,
                                                       LH_TABLE_U1, r1);
         }
     }

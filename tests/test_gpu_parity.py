@@ -210,6 +210,78 @@ def test_hogwild_c1_auc_matches_oracle():
     assert abs(auc_uu - gold["auc_uu"]) <= 0.005
 
 
+_C2 = {}
+
+
+def _c2():
+    if not _C2:
+        _C2["g"] = config_graph("C2")
+    return _C2["g"]
+
+
+def _held_out_aucs(tr, hs, hd, neg, orders):
+    lh = _lh()
+    out = {}
+    if orders & 2:
+        U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+        C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+        out["uc"] = oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg))
+        uu = (dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
+        out["uu"] = oracle.auc(*uu)
+    if orders & 1:
+        U1 = tr.read(lh.LH_TABLE_U1).cpu().numpy()
+        o1 = (dot_rows(U1, U1, hs, hd), dot_rows(U1, U1, hs, neg))
+        out["o1"] = oracle.auc(*o1)
+    if orders == 3:
+        out["concat"] = oracle.auc(uu[0] + o1[0], uu[1] + o1[1])
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_hogwild_c2_auc_matches_oracle(dtype):
+    """C2 (and C3 for bfloat16) at full size, in the launch configuration bench.py times:
+    every held-out AUC within 0.005 of the binary64 oracle's SEQ run."""
+    gold = json.load(open(os.path.join(GOLDEN, "c2_oracle_auc.json")))
+    g, hs, hd, neg = _c2()
+    tr = trainer_for(g, d=128, K=5, orders=3, dtype=dtype, seed=gold["seed"], total_samples=gold["T"])
+    tr.train_steps(0, gold["T"])
+    tr.check()
+    got = _held_out_aucs(tr, hs, hd, neg, 3)
+    print(f"C2 {dtype} hogwild: " + " ".join(f"{k} {v:.4f} (oracle {gold['auc_' + k]:.4f})" for k, v in got.items()),
+          flush=True)
+    for k, v in got.items():
+        assert abs(v - gold["auc_" + k]) <= 0.005, (k, v, gold["auc_" + k])
+
+
+def test_snapshot_c2_prefix_within_1e5():
+    """The first 2^20 samples of C2 in SNAPSHOT mode (B = 65536), binary32 GPU vs binary64 oracle."""
+    lh = _lh()
+    g, _, _, _ = _c2()
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    count, B = 1 << 20, 65536
+    tr = trainer_for(g, d=128, K=5, orders=3, seed=2, total_samples=200_000_000, mode="snapshot", batch=B)
+    tr.train_steps(0, count)
+    tr.check()
+    m = oracle.Model(t, d=128, K=5, orders=3, T=200_000_000, seed=2)
+    m.train(0, count, "snapshot", B)
+    for name, tab, ref in (("U", lh.LH_TABLE_U, m.U), ("C", lh.LH_TABLE_C, m.C), ("U1", lh.LH_TABLE_U1, m.U1)):
+        err = max_row_rel_err(tr.read(tab).cpu().numpy(), ref)
+        print(f"snapshot C2 prefix table {name}: max row rel err {err:.3e}", flush=True)
+        assert err <= 1e-5, (name, err)
+
+
+def test_sampler_c2_sampled_indices():
+    """C2 at full size: tuples at sampled indices, including past 2^32, equal the oracle's."""
+    g, _, _, _ = _c2()
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    tr = trainer_for(g, d=128, K=5, orders=3, seed=2, total_samples=10, init=False)
+    _alias_equal(tr, t)
+    for first in (0, 199_999_000, 2**32 + 12345, 2**41 + 3):
+        u, v, neg = tr.sample(first, 1000)
+        ou, ov, oneg = oracle.sample(t, seed=2, graph_id=0, K=5, first=first, count=1000)
+        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(neg.cpu().numpy(), oneg)
+
+
 # ---------------------------------------------------------------------------
 # Error paths forced from the host.
 # ---------------------------------------------------------------------------
