@@ -21,11 +21,15 @@
  *   - The caller owns every buffer it passes in; the library never frees caller
  *     memory.  A handle owns only small host metadata and one int64 device status word.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Every call
- *     enqueues its work on the handle's stream and returns without synchronising,
- *     except lh_check, lh_export_alias and lh_create/lh_destroy, which synchronise.
+ *     enqueues its work on the handle's stream; the calls whose comment says so
+ *     (lh_set_graph, lh_build_alias, lh_export_alias, lh_tune, lh_check,
+ *     lh_last_train_ms, lh_destroy and the batch calls that report results) synchronise
+ *     it, the others return without waiting.
  *   - Argument errors are detected on the host before any GPU work and returned at
- *     once.  Errors in the data (an ID >= n, a NaN or negative weight, a zero total
- *     weight) are recorded on the device and reported by lh_check.
+ *     once.  Errors in the graph (an ID >= n, a NaN or negative weight, a zero total
+ *     weight) are found by lh_set_graph / lh_build_alias, which wait for their check and
+ *     return them; an imported alias entry outside [0, N) is recorded on the device and
+ *     reported by lh_check.
  *   - No call throws; every call returns an lh_status.  A handle must not be used
  *     from two threads at once; distinct handles are independent.
  *   - Tables are row-major [n x d] with rows of d elements (d % 8 == 0), binary32 or
@@ -74,10 +78,14 @@ typedef struct {
     int32_t mode;       /* LH_HOGWILD or LH_SNAPSHOT                                        */
     int32_t graph_id;   /* low 32 bits of key word 1 (one stream per graph)                 */
     int64_t batch;      /* SNAPSHOT batch B (samples [bB, (b+1)B) share one snapshot)      */
-    double hot_rate;    /* HOGWILD: a row whose expected number of concurrent writers
-                           (samples in flight x probability a sample touches it) reaches
-                           hot_rate is updated with atomic increments, other rows with
-                           plain stores.  <= 0: every row atomic; >= 1e30: none.        */
+    double hot_rate;    /* HOGWILD: a row r is "hot" when W p_r >= hot_rate, p_r = the
+                           probability that one sample touches r (from the degrees of the
+                           last lh_build_alias), W = samples in flight + samples for which
+                           a row stays cached in one XCD's L2 (unbounded when the tables
+                           fit in one L2: every touched row is hot).  Hot rows take
+                           coherent atomic increments, the others plain stores.  Rows of
+                           imported alias tables are hot.  <= 0: every row atomic;
+                           >= 1e30: none.                                                */
     double max_conflicts; /* HOGWILD: the launch keeps F samples in flight with
                            F (2 + K) / n_active <= max_conflicts, n_active = nodes with an
                            arc, so that a row of average traffic has at most this many
@@ -106,14 +114,19 @@ LH_API lh_status lh_bind(lh_handle *h, void *workspace, size_t bytes, void *cons
                   void *stream);
 
 /* The graph: n nodes, m arcs (src[a] -> dst[a], weight w[a]); device arrays that must
- * stay valid until lh_build_alias's work has run.  An undirected edge is two arcs.
- * Endpoint and weight checks run on the device (reported by lh_check). */
+ * stay valid until lh_build_alias has returned.  An undirected edge is two arcs.  The
+ * endpoints and weights are checked by a kernel and the call synchronises the stream:
+ * LH_ERR_OUT_OF_RANGE for an endpoint outside [0, n), LH_ERR_ZERO_WEIGHT for a negative,
+ * NaN or infinite weight; the handle then has no graph. */
 LH_API lh_status lh_set_graph(lh_handle *h, int64_t n, int64_t m, const int32_t *src,
                        const int32_t *dst, const float *w);
 
 /* Build the edge alias table over the m arcs (weights w) and the negative alias table
  * over the n nodes (weights out-degree^0.75, Eq. (1)) with the binary64 canonical
- * chunked scan.  scratch: device, >= *scratch bytes from lh_workspace_size. */
+ * chunked scan, and the per-node touch rates the Hogwild write path is chosen by.
+ * scratch: device, >= *scratch bytes from lh_workspace_size, free once the call has
+ * returned (it synchronises the stream).  LH_ERR_ZERO_WEIGHT when the arcs' total weight
+ * is zero (or m == 0). */
 LH_API lh_status lh_build_alias(lh_handle *h, void *scratch, size_t scratch_bytes);
 
 /* Replace (import) or copy out (export) one alias table: which = LH_ALIAS_EDGE (N = m)

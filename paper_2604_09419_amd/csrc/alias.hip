@@ -189,7 +189,9 @@ struct RecOut {
     const uint8_t *heat;  // per node; NULL: every node 255 (never hot)
 };
 
-__device__ __forceinline__ uint32_t heat_of(const RecOut &o, long long v) { return o.heat ? o.heat[v] : 255u; }
+// Without a heat array (imported alias tables carry no degrees) every row is taken as hot:
+// the coherent atomic update is correct for any row, only slower.
+__device__ __forceinline__ uint32_t heat_of(const RecOut &o, long long v) { return o.heat ? o.heat[v] : 0u; }
 
 __device__ __forceinline__ void write_rec(const RecOut &o, long long i, unsigned long long thr,
                                           int32_t al)

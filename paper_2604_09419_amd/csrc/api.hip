@@ -44,6 +44,11 @@ GraphDev graph_dev(const lh_handle *h)
     g.max_in_flight = 0.0;
     if (h->p.max_conflicts > 0.0 && h->n_active > 0)
         g.max_in_flight = h->p.max_conflicts * (double)h->n_active / (double)(h->p.K + 2);
+    const double b = h->p.dtype == LH_FP32 ? 4.0 : 2.0;
+    const double ntab = h->p.orders == LH_ORDER12 ? 3.0 : (h->p.orders == LH_ORDER2 ? 2.0 : 1.0);
+    const double nord = h->p.orders == LH_ORDER12 ? 2.0 : 1.0;
+    const double rows = (double)(h->n_active > 0 ? h->n_active : h->n);
+    g.resid = l2_residency(h->l2_bytes, rows * h->p.d * b * ntab, nord * (h->p.K + 2) * h->p.d * b);
     return g;
 }
 
@@ -161,6 +166,9 @@ lh_status lh_create(lh_handle **out, const lh_params *p, int device)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         h->num_cu = cus;
+    int l2 = 0;
+    if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, device) == hipSuccess && l2 > 0)
+        h->l2_bytes = (double)l2;
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         delete h;
         return LH_ERR_HIP;

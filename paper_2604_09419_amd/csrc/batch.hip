@@ -261,6 +261,7 @@ struct lh_batch {
     std::vector<lh::BatchDesc> desc;
     std::vector<unsigned long long> sched;
     int variant = 0, blocks_per_cu = 8;
+    unsigned grid = 1;  // blocks of the persistent kernel (set with the schedule)
     unsigned long long item_samples = 8192;
     unsigned long long total_items = 0;
     hipGraph_t graph = nullptr;
@@ -271,9 +272,10 @@ struct lh_batch {
 
 namespace lh {
 
-// Samples in flight of a batched launch: resident wavefronts x groups per wavefront of
-// the narrower tile configuration (an upper bound, so hot rows are over- not under-counted).
-static double batch_in_flight(const lh_batch *b, int variant, int bpc)
+// Resident blocks per CU and lanes per sample of the narrower tile configuration of a
+// batched kernel variant (the narrower one gives the upper bound on samples in flight, so
+// hot rows are over- rather than under-counted).
+static int batch_occupancy(const lh_batch *b, int variant, int *ls_out)
 {
     int occ = 0, ls = 8;
     const bool k5 = b->K <= 5;
@@ -290,24 +292,45 @@ static double batch_in_flight(const lh_batch *b, int variant, int bpc)
         else { if (variant == 0) LH_OCC(float, 8, 0) else LH_OCC(float, 8, 1) }
     }
 #undef LH_OCC
-    if (occ < 1) occ = 8;
-    double blocks = std::min<double>((double)b->num_cu * bpc, (double)b->num_cu * occ);
-    return blocks * 4.0 * (64.0 / ls);
+    *ls_out = ls;
+    return occ < 1 ? 8 : occ;
 }
 
+// The schedule of a batched launch, its grid and each graph's heat threshold.  Graph g
+// holds the share phi_g = T_g / sum T of the samples in flight (the schedule interleaves
+// the graphs in proportion), so the grid is lowered until phi_g F stays within every
+// graph's staleness cap.  The L2 residency window of each graph is the one it has when
+// trained alone: other graphs' lines can only evict its lines sooner, so this errs
+// towards more hot rows (a lower bound from the graphs' summed footprint was measured
+// to leave rows of small graphs stale).
 static void batch_items(lh_batch *b, unsigned long long item_samples, bool dry, unsigned long long probe)
 {
-    unsigned long long acc = 0;
-    const double F = batch_in_flight(b, b->variant, b->blocks_per_cu);
+    unsigned long long acc = 0, total = 0;
+    for (int i = 0; i < b->G; ++i) {
+        BatchDesc &D = b->desc[i];
+        D.g = graph_dev(b->hs[i]);
+        D.limit = dry ? (probe < D.g.T ? probe : D.g.T) : D.g.T;
+        total += D.limit;
+    }
+    int ls = 8;
+    const int occ = batch_occupancy(b, b->variant, &ls);
+    const double per_block = 4.0 * (64.0 / ls);
+    double grid = (double)b->num_cu * b->blocks_per_cu;
+    for (int i = 0; i < b->G; ++i) {
+        const double phi = total ? (double)b->desc[i].limit / (double)total : 0.0;
+        const double cap = b->desc[i].g.max_in_flight;
+        if (cap > 0.0 && phi > 0.0) grid = std::min(grid, std::max(1.0, std::floor(cap / phi / per_block)));
+    }
+    b->grid = (unsigned)std::max(1.0, grid);
+    const double F = std::min((double)b->grid, (double)b->num_cu * occ) * per_block;
     // (position in [0, 1), graph, chunk): chunk i of a graph with c chunks sits at (i + 1/2) / c.
     std::vector<std::pair<double, unsigned long long>> order;
     for (int i = 0; i < b->G; ++i) {
         BatchDesc &D = b->desc[i];
-        D.g = graph_dev(b->hs[i]);
-        D.g.hot_heat = hot_heat_for(F, D.g.hot_rate);
+        const double phi = total ? (double)D.limit / (double)total : 0.0;
+        D.g.hot_heat = hot_heat_for(phi * F + D.g.resid, D.g.hot_rate);
         D.g.max_in_flight = 0.0;
         D.g.eta_scale = dry ? 0.0f : 1.0f;
-        D.limit = dry ? (probe < D.g.T ? probe : D.g.T) : D.g.T;
         D.item0 = acc;
         const unsigned long long c = (D.limit + item_samples - 1) / item_samples;
         for (unsigned long long k = 0; k < c; ++k)
@@ -335,7 +358,8 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
     a.done = b->d_ctr + 1;
     hipStream_t s = b->stream;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a.queue, a.done, b->G);
-    dim3 grid((unsigned)(b->num_cu * bpc)), block(256);
+    (void)bpc;
+    dim3 grid(b->grid), block(256);
     const bool k5 = b->K <= 5;
 #define LH_BL(TT, KM, V) hipLaunchKernelGGL((k_batch<TT, KM, V>), grid, block, 0, s, a)
     if (b->dtype == LH_BF16) {

@@ -26,6 +26,7 @@ struct GraphDev {
     int hot_heat;              // rows with heat <= hot_heat take atomic increments (-1: none)
     double hot_rate;           // host side: the threshold hot_heat is derived from per launch
     double max_in_flight;      // host side: cap on samples in flight (0: none)
+    double resid;              // host side: samples a row stays cached in one XCD's L2 (inf: whole launch)
 };
 
 // A kernel configuration: lanes per sample and 16-byte chunks per lane.
@@ -46,6 +47,20 @@ struct ScratchLayout {
 };
 
 WsLayout ws_layout(const lh_params &p, long long n, long long m);
+
+// XCDs of one MI355X; each has its own L2, and the L2s are not kept coherent with each
+// other for ordinary loads and stores within a kernel.
+constexpr int kXcds = 8;
+
+// Samples (chip-wide) for which a row line, once in one XCD's L2, stays there: each XCD
+// sees one sample in kXcds and each sample brings at most bytes_per_sample of new lines,
+// so a line survives at least kXcds * l2_bytes / bytes_per_sample samples.  Tables whose
+// footprint fits in one L2 stay cached for the whole launch (infinity).
+inline double l2_residency(double l2_bytes, double footprint, double bytes_per_sample)
+{
+    if (footprint <= l2_bytes) return __builtin_inf();
+    return bytes_per_sample > 0.0 ? (double)kXcds * l2_bytes / bytes_per_sample : 0.0;
+}
 ScratchLayout scratch_layout(long long n, long long m);
 
 constexpr int RADIX_ITEMS = 16;
@@ -58,6 +73,7 @@ struct lh_handle {
     lh_params p{};
     int device = 0;
     int num_cu = 256;
+    double l2_bytes = 4194304.0;  // L2 bytes of one XCD
     hipStream_t stream = nullptr;
     bool bound = false, graph_set = false, edge_ready = false, neg_ready = false;
     char *ws = nullptr;

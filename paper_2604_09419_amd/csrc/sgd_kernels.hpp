@@ -45,13 +45,17 @@ inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_pe
     return (unsigned)blocks;
 }
 
-// Heat threshold for a launch with F samples in flight: a row is hot when F p_r reaches
-// hot_rate, i.e. when floor(-log2 p_r) <= floor(log2(F / hot_rate)).
-inline int hot_heat_for(double F, double hot_rate)
+// Heat threshold for a launch whose rows stay exposed for a window of W samples (those in
+// flight plus those for which a row stays cached in one XCD's L2; infinite when the tables
+// fit in one L2): a row is hot when W p_r reaches hot_rate, i.e. when
+// floor(-log2 p_r) <= floor(log2(W / hot_rate)).  hot_rate <= 0 makes every row hot,
+// hot_rate >= 1e30 none.
+inline int hot_heat_for(double W, double hot_rate)
 {
     if (!(hot_rate > 0.0)) return 255;
-    if (hot_rate >= 1e30 || F <= 0.0) return -1;
-    double t = std::floor(std::log2(F / hot_rate));
+    if (hot_rate >= 1e30 || !(W > 0.0)) return -1;
+    if (std::isinf(W)) return 255;
+    double t = std::floor(std::log2(W / hot_rate));
     if (t < -1.0) return -1;
     if (t > 255.0) return 255;
     return (int)t;
@@ -104,7 +108,7 @@ hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c
         F = samples_in_flight(kern, grid, num_cu, lps);
     }
     GraphDev gl = g;
-    gl.hot_heat = hot_heat_for(F, g.hot_rate);
+    gl.hot_heat = hot_heat_for(F + g.resid, g.hot_rate);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, gl, first, end);
     return hipGetLastError();
 }

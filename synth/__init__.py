@@ -13,5 +13,6 @@ from .graphs import (  # noqa: F401
     auc_negatives,
     batch_graph_specs,
     batch_graph,
+    small_batch,
     CONFIGS,
 )

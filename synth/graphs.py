@@ -254,3 +254,22 @@ def batch_graph(spec: dict) -> Graph:
     g = rmat_graph(spec["scale"], spec["n"], spec["m"], spec["seed"] + 100_000, True, "lognormal")
     g.meta.update(spec)
     return g
+
+
+def small_batch(G: int = 6):
+    """A few small graphs for tests of the batched launch: graph gi has n drawn from
+    U[2000, 20000), m = n * U[8, 16) unique directed R-MAT arcs (seed 700 + gi), unit
+    weights, d = 64 for even gi and 128 for odd gi, a 1 % held-out split (seed 800 + gi)
+    with evaluation negatives (seed 900 + gi), T = 20 training epochs, training seed
+    10 + gi and graph id gi.  Returns one dict per graph."""
+    rng = np.random.default_rng(0)
+    out = []
+    for gi in range(G):
+        n = int(rng.integers(2000, 20000))
+        m = int(n * rng.uniform(8, 16))
+        g = rmat_graph(int(np.ceil(np.log2(n))), n, m, seed=700 + gi)
+        tr, hs, hd = holdout_split(g, seed=800 + gi)
+        neg = auc_negatives(g.n, g.src, g.dst, hs, seed=900 + gi)
+        out.append(dict(graph=tr, held_src=hs, held_dst=hd, neg_dst=neg, T=20 * tr.m,
+                        d=64 if gi % 2 == 0 else 128, seed=10 + gi, graph_id=gi))
+    return out

@@ -48,3 +48,14 @@ def test_batch_specs():
     assert all(1000 <= s["n"] <= 2_000_000 and s["d"] in (64, 128) for s in specs)
     assert all(8 <= s["m"] / s["n"] <= 32.01 for s in specs)
     assert specs == batch_graph_specs()
+
+
+def test_small_batch_matches_stored_oracle_aucs():
+    """The stored batch oracle AUCs were computed on exactly these graphs."""
+    import json
+    import os
+    from synth import small_batch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch6_oracle_auc.json")))
+    for it, ref in zip(small_batch(6), gold["graphs"]):
+        assert (it["graph"].n, it["graph"].m, it["held_src"].size, it["d"], it["T"], it["seed"]) == \
+            (ref["n"], ref["m_train"], ref["held_out"], ref["d"], ref["T"], ref["seed"])
