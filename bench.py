@@ -42,6 +42,51 @@ def algorithmic_bytes_per_sample(d: int, K: int, orders: int, elem_bytes: int) -
     return n_orders * 2 * (2 + K) * d * elem_bytes + 32 + 16 * K
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_hogwild_c2_fp32_hbm_traffic.md")
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of every source the library's kernels are built from: the HIP sources and
+    headers, the C header and the build script."""
+    import glob
+    import hashlib
+    pkg = os.path.join(ROOT, "paper_2604_09419_amd")
+    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*.hip")) + glob.glob(os.path.join(pkg, "csrc", "*.hpp")))
+    files += [os.path.join(ROOT, "include", "linehip.h"), os.path.join(pkg, "build.py")]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        h.update(b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
+def measured_traffic(path: str, kernel_config: dict, total_samples: int):
+    """HBM bytes per launch of the training kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
+    when the kernel sources, the kernel configuration or T differ from those the
+    counters were taken with."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            k, sep, v = line.strip().partition(": ")
+            if sep:
+                rec[k] = v.strip()
+    try:
+        cfg = [int(x) for x in rec["kernel_config"].split()]
+        ok = (rec["kernel_sources_sha256"] == kernel_sources_sha256()
+              and cfg == [kernel_config["lanes_per_sample"], kernel_config["chunks_per_lane"],
+                          kernel_config["blocks_per_cu"]]
+              and int(rec["total_samples"]) == int(total_samples))
+        return float(rec["traffic_bytes_per_launch"]) if ok else None
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -289,6 +334,7 @@ def main():
     ms_kern = sum(kern_ms) / len(kern_ms)
     bps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 4)
     achieved = bps * T / (ms_kern * 1e-3) / 1e9
+    traffic = measured_traffic(TRAFFIC_PROFILE, tr.kernel_config(), T)
 
     result = {
         "metric": METRIC,
@@ -313,8 +359,10 @@ def main():
         "train_only": {"samples_per_s": T / (ms_kern * 1e-3), "ms": ms_kern},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
             "kernel": "k_hogwild (binary32, orders 1+2)", "bytes_per_sample": bps,
+            "algorithmic_bytes_per_launch": bps * T,
+            "traffic_over_algorithmic": None if traffic is None else traffic / (bps * T),
         },
     }
     if not args.no_auc:
