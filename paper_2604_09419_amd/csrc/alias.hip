@@ -70,23 +70,35 @@ __global__ void k_degrees(const int32_t *src, const int32_t *dst, long long m, i
 }
 
 // Heat of node r (see common.hpp): floor(-log2 p_r), p_r = (out + in) / m + K nu_r / W_nu.
-// It only chooses between two write paths of the training kernel, so it is computed in
-// ordinary binary64 arithmetic.
-__global__ void k_heat(const int32_t *deg, const int32_t *indeg, const double *nu, const double *nu_scan,
-                       long long n, long long m, int K, uint8_t *heat, unsigned long long *n_active)
+// It only chooses between the write paths of the training kernel, so it is computed in
+// ordinary binary64 arithmetic.  cnt[0] counts the nodes with an arc, cnt[1 + h] the
+// nodes of heat h (a per-block histogram in LDS, then one atomic per bin).  256 threads.
+__global__ void __launch_bounds__(256) k_heat(const int32_t *deg, const int32_t *indeg, const double *nu,
+                                              const double *nu_scan, long long n, long long m, int K, uint8_t *heat,
+                                              unsigned long long *cnt)
 {
-    long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    if (deg[r] + indeg[r] > 0) atomicAdd(n_active, 1ull);
-    double Wn = nu_scan[n - 1];
-    double p = (double)(deg[r] + indeg[r]) / (double)m;
-    if (Wn > 0.0) p += (double)K * nu[r] / Wn;
-    int hv = 255;
-    if (p > 0.0) {
-        double t = floor(-log2(p));
-        hv = t < 0.0 ? 0 : (t > 255.0 ? 255 : (int)t);
+    __shared__ unsigned int hist[256];
+    __shared__ unsigned int active;
+    hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) active = 0u;
+    __syncthreads();
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        if (deg[r] + indeg[r] > 0) atomicAdd(&active, 1u);
+        const double Wn = nu_scan[n - 1];
+        double p = (double)(deg[r] + indeg[r]) / (double)m;
+        if (Wn > 0.0) p += (double)K * nu[r] / Wn;
+        int hv = 255;
+        if (p > 0.0) {
+            const double t = floor(-log2(p));
+            hv = t < 0.0 ? 0 : (t > 254.0 ? 254 : (int)t);
+        }
+        heat[r] = (uint8_t)hv;
+        atomicAdd(&hist[hv], 1u);
     }
-    heat[r] = (uint8_t)hv;
+    __syncthreads();
+    if (hist[threadIdx.x]) atomicAdd(&cnt[1 + threadIdx.x], (unsigned long long)hist[threadIdx.x]);
+    if (threadIdx.x == 0 && active) atomicAdd(&cnt[0], (unsigned long long)active);
 }
 
 __global__ void k_zero_i32(int32_t *p, long long n)
@@ -95,7 +107,16 @@ __global__ void k_zero_i32(int32_t *p, long long n)
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_zero_u64(unsigned long long *p) { p[0] = 0ull; }
+__global__ void k_zero_u64(unsigned long long *p, int count)
+{
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_fill_u8(uint8_t *p, long long n, uint8_t v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 __global__ void k_edge_weights(const float *w, long long m, double *wq)
 {
@@ -269,7 +290,7 @@ static lh_status build_one(lh_handle *h, int which, const ScratchLayout &L, char
     int32_t *idx = (int32_t *)(sc + L.idx);
     int32_t *lpos = (int32_t *)(sc + L.lpos);
     int32_t *deg = (int32_t *)(sc + L.deg);
-    const uint8_t *heat = (const uint8_t *)(sc + L.heat);
+    const uint8_t *heat = (const uint8_t *)(h->ws + h->lay.nheat);
     double *lev = (double *)(sc + L.lev);
     int32_t *ilev = (int32_t *)(sc + L.ilev);
     dim3 blk(256), grd((unsigned)LH_CDIV(N, 256));
@@ -335,14 +356,15 @@ lh_status build_alias(lh_handle *h, void *scratch, size_t bytes)
         hipLaunchKernelGGL(k_neg_weights, gn, blk, 0, s, deg, h->n, wq);
         chunk_scan<OpNeumaier>(wq, dx, h->n, lev, s);
         unsigned long long *cnt = (unsigned long long *)(sc + L.cnt);
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
-        hipLaunchKernelGGL(k_heat, gn, blk, 0, s, deg, indeg, wq, dx, h->n, h->m, h->p.K, (uint8_t *)(sc + L.heat),
-                           cnt);
-        unsigned long long na = 0;
-        hipError_t e = hipMemcpyAsync(&na, cnt, sizeof(na), hipMemcpyDeviceToHost, s);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(320), 0, s, cnt, 257);
+        hipLaunchKernelGGL(k_heat, gn, blk, 0, s, deg, indeg, wq, dx, h->n, h->m, h->p.K,
+                           (uint8_t *)(h->ws + h->lay.nheat), cnt);
+        unsigned long long host[257];
+        hipError_t e = hipMemcpyAsync(host, cnt, sizeof(host), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(h, e, "degree pass");
-        h->n_active = (long long)na;
+        h->n_active = (long long)host[0];
+        for (int v = 0; v < 256; ++v) h->heat_count[v] = host[1 + v];
     }
     lh_status st = build_one(h, LH_ALIAS_NEG, L, (char *)scratch);
     if (st != LH_OK) return st;
@@ -396,6 +418,12 @@ lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32
     if (N > 0)
         hipLaunchKernelGGL(k_import, dim3((unsigned)LH_CDIV(N, 256)), dim3(256), 0, h->stream,
                            (const unsigned long long *)thr, alias, N, o, h->status);
+    // Imported tables come without degrees: every node is taken as hot (heat 0).
+    if (h->n > 0)
+        hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)LH_CDIV(h->n, 256)), dim3(256), 0, h->stream,
+                           (uint8_t *)(h->ws + h->lay.nheat), h->n, (uint8_t)0);
+    for (int v = 0; v < 256; ++v) h->heat_count[v] = 0;
+    h->heat_count[0] = (unsigned long long)h->n;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "alias import");
     if (which == LH_ALIAS_EDGE)

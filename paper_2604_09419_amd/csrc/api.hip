@@ -49,6 +49,10 @@ GraphDev graph_dev(const lh_handle *h)
     const double nord = h->p.orders == LH_ORDER12 ? 2.0 : 1.0;
     const double rows = (double)(h->n_active > 0 ? h->n_active : h->n);
     g.resid = l2_residency(h->l2_bytes, rows * h->p.d * b * ntab, nord * (h->p.K + 2) * h->p.d * b);
+    ShadowCtx sc;
+    const bool shadowed = shadow_ctx(h, &sc);
+    for (int t = 0; t < 3; ++t) g.shadow[t] = shadowed ? sc.shadow[t] : nullptr;
+    g.slot = shadowed ? sc.slot : nullptr;
     return g;
 }
 
@@ -303,8 +307,10 @@ lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count)
     if (e != hipSuccess) return hip_fail(h, e, "event");
     lh_status st = LH_OK;
     if (h->p.mode == LH_HOGWILD) {
-        e = launch_hogwild(graph_dev(h), h->p.dtype, h->p.orders, h->cfg, first, first + count, h->num_cu, h->status,
-                           h->stream);
+        ShadowCtx sc;
+        const bool shadowed = shadow_ctx(h, &sc);
+        e = launch_hogwild(graph_dev(h), h->p.dtype, h->p.orders, h->cfg, first, first + count, h->num_cu,
+                           shadowed ? &sc : nullptr, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "hogwild launch");
     } else {
         st = train_snapshot(h, first, count);

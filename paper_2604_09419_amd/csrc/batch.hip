@@ -137,11 +137,11 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
                 c.blocks_per_cu = bpc;
                 if (!cfg_supported(h->p.dtype, h->p.d, c)) continue;
                 // warm-up, then timed
-                hipError_t er = launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe / 4, h->num_cu, h->status,
+                hipError_t er = launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe / 4, h->num_cu, nullptr,
                                                h->stream);
                 if (er != hipSuccess) continue;
                 (void)hipEventRecord(e0, h->stream);
-                (void)launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe, h->num_cu, h->status, h->stream);
+                (void)launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe, h->num_cu, nullptr, h->stream);
                 (void)hipEventRecord(e1, h->stream);
                 if (hipEventSynchronize(e1) != hipSuccess) continue;
                 float ms = 0;
@@ -357,6 +357,14 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
     a.queue = b->d_ctr;
     a.done = b->d_ctr + 1;
     hipStream_t s = b->stream;
+    // bfloat16 graphs: each graph's hot rows move into its binary32 shadow for the launch.
+    for (int i = 0; i < b->G; ++i) {
+        ShadowCtx sc;
+        if (shadow_ctx(b->hs[i], &sc)) {
+            hipError_t e = shadow_begin(sc, b->desc[i].g.hot_heat, s);
+            if (e != hipSuccess) return e;
+        }
+    }
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a.queue, a.done, b->G);
     (void)bpc;
     dim3 grid(b->grid), block(256);
@@ -376,7 +384,12 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
         }
     }
 #undef LH_BL
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    for (int i = 0; i < b->G && e == hipSuccess; ++i) {
+        ShadowCtx sc;
+        if (shadow_ctx(b->hs[i], &sc)) e = shadow_end(sc, b->desc[i].g.hot_heat, 0, s);
+    }
+    return e;
 }
 
 static hipError_t upload_desc(lh_batch *b)

@@ -27,6 +27,11 @@ struct GraphDev {
     double hot_rate;           // host side: the threshold hot_heat is derived from per launch
     double max_in_flight;      // host side: cap on samples in flight (0: none)
     double resid;              // host side: samples a row stays cached in one XCD's L2 (inf: whole launch)
+    // bfloat16 Hogwild: binary32 shadow rows of the hot rows ([cap x d] per table) and the
+    // per-node slot map (slot >= 0: the row lives in the shadow for this launch).  NULL
+    // for binary32 tables and SNAPSHOT.
+    float *shadow[3];
+    const int32_t *slot;
 };
 
 // A kernel configuration: lanes per sample and 16-byte chunks per lane.
@@ -36,17 +41,43 @@ struct TileCfg {
 
 struct WsLayout {
     size_t status = 0, erec = 0, nrec = 0;
+    size_t nheat = 0;                                   // [n] bytes: per-node heat
+    size_t slot = 0, srows = 0, shadow = 0;             // bfloat16 Hogwild shadow (else 0)
+    long long shadow_cap = 0;                           // shadow rows per table
     size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, contrib = 0, hist = 0, ilev = 0,
            seg = 0, segid = 0, total = 0;
     long long entries = 0, hist_n = 0, ilev_n = 0;
 };
 
 struct ScratchLayout {
-    size_t wq = 0, dx = 0, idx = 0, lpos = 0, deg = 0, indeg = 0, heat = 0, cnt = 0, lev = 0, ilev = 0, total = 0;
+    size_t wq = 0, dx = 0, idx = 0, lpos = 0, deg = 0, indeg = 0, cnt = 0, lev = 0, ilev = 0, total = 0;
     long long N = 0, lev_n = 0;
 };
 
 WsLayout ws_layout(const lh_params &p, long long n, long long m);
+
+// Shadow rows per table of a bfloat16 Hogwild handle with n nodes: every node of a graph
+// of up to 2^17 nodes, else one node in 16.  The hot set of a launch is trimmed to fit.
+inline long long shadow_capacity(long long n)
+{
+    long long c = (n + 15) / 16;
+    if (c < (1ll << 17)) c = 1ll << 17;
+    return c < n ? c : n;
+}
+
+// Host view of one handle's shadow for a launch (see shadow_begin / shadow_end).
+struct ShadowCtx {
+    const uint8_t *nheat;       // [n] per-node heat
+    int32_t *slot;              // [n]
+    int32_t *srows;             // [cap] node of each slot
+    float *shadow[3];           // [cap x d] per table, NULL when the table is unused
+    void *tab[3];               // the bfloat16 tables
+    unsigned int *counter;      // device word: slots handed out
+    const unsigned long long *heat_count;  // host [256]: nodes per heat value
+    long long n, cap;
+    int d;
+    unsigned long long seed, sr_key;
+};
 
 // XCDs of one MI355X; each has its own L2, and the L2s are not kept coherent with each
 // other for ordinary loads and stores within a kernel.
@@ -81,6 +112,7 @@ struct lh_handle {
     void *tab[3] = {nullptr, nullptr, nullptr};
     long long n = 0, m = 0;
     long long n_active = 0;  // nodes with at least one arc (from the last alias build)
+    unsigned long long heat_count[256] = {};  // nodes per heat value (last build or import)
     const int32_t *src = nullptr, *dst = nullptr;
     const float *w = nullptr;
     lh::WsLayout lay;
@@ -111,6 +143,13 @@ TileCfg default_cfg(int dtype, int d);
 bool cfg_supported(int dtype, int d, const TileCfg &c);
 hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c,
                           unsigned long long first, unsigned long long end, int num_cu,
-                          unsigned int *status, hipStream_t s);
+                          const ShadowCtx *sc, hipStream_t s);
+// The shadow context of a bfloat16 Hogwild handle (false for other handles).
+bool shadow_ctx(const lh_handle *h, ShadowCtx *out);
+// Before a launch: trim hot_heat so the hot set fits the shadow, give each hot node a
+// slot (others -1) and widen its rows into the shadow.  After: round the shadow rows back
+// into the tables (stochastic rounding keyed by `first`).
+hipError_t shadow_begin(const ShadowCtx &sc, int hot_heat, hipStream_t s);
+hipError_t shadow_end(const ShadowCtx &sc, int hot_heat, unsigned long long first, hipStream_t s);
 lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count);
 }  // namespace lh

@@ -30,6 +30,14 @@ WsLayout ws_layout(const lh_params &p, long long n, long long m)
     L.status = carve(off, 256);
     L.erec = carve(off, sizeof(EdgeRec) * (size_t)(m > 0 ? m : 1));
     L.nrec = carve(off, sizeof(NegRec) * (size_t)(n > 0 ? n : 1));
+    L.nheat = carve(off, (size_t)(n > 0 ? n : 1));
+    if (p.mode == LH_HOGWILD && p.dtype == LH_BF16) {
+        const size_t ntab = p.orders == LH_ORDER12 ? 3 : (p.orders == LH_ORDER2 ? 2 : 1);
+        L.shadow_cap = shadow_capacity(n > 0 ? n : 1);
+        L.slot = carve(off, 4 * (size_t)(n > 0 ? n : 1));
+        L.srows = carve(off, 4 * (size_t)L.shadow_cap);
+        L.shadow = carve(off, 4 * (size_t)L.shadow_cap * (size_t)p.d * ntab);
+    }
     if (p.mode == LH_SNAPSHOT) {
         long long nord = p.orders == 3 ? 2 : 1;
         long long E = p.batch * nord * (long long)(p.K + 2);
@@ -64,8 +72,7 @@ ScratchLayout scratch_layout(long long n, long long m)
     L.lpos = carve(off, 4 * (size_t)N);
     L.deg = carve(off, 4 * (size_t)(n > 0 ? n : 1));
     L.indeg = carve(off, 4 * (size_t)(n > 0 ? n : 1));
-    L.heat = carve(off, (size_t)(n > 0 ? n : 1));
-    L.cnt = carve(off, 8);
+    L.cnt = carve(off, 8 * 257);
     L.lev_n = scan_levels_size(N);
     L.lev = carve(off, 8 * (size_t)L.lev_n);
     L.ilev = carve(off, 4 * (size_t)L.lev_n);
@@ -111,16 +118,16 @@ bool cfg_supported(int dtype, int d, const TileCfg &c)
 }
 
 hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c, unsigned long long first,
-                          unsigned long long end, int num_cu, unsigned int *, hipStream_t s)
+                          unsigned long long end, int num_cu, const ShadowCtx *sc, hipStream_t s)
 {
     if (dtype == LH_FP32) {
-        if (orders == 1) return launch_hogwild_t<float, 1>(g, c, first, end, num_cu, s);
-        if (orders == 2) return launch_hogwild_t<float, 2>(g, c, first, end, num_cu, s);
-        return launch_hogwild_t<float, 3>(g, c, first, end, num_cu, s);
+        if (orders == 1) return launch_hogwild_t<float, 1>(g, c, first, end, num_cu, nullptr, s);
+        if (orders == 2) return launch_hogwild_t<float, 2>(g, c, first, end, num_cu, nullptr, s);
+        return launch_hogwild_t<float, 3>(g, c, first, end, num_cu, nullptr, s);
     }
-    if (orders == 1) return launch_hogwild_t<uint16_t, 1>(g, c, first, end, num_cu, s);
-    if (orders == 2) return launch_hogwild_t<uint16_t, 2>(g, c, first, end, num_cu, s);
-    return launch_hogwild_t<uint16_t, 3>(g, c, first, end, num_cu, s);
+    if (orders == 1) return launch_hogwild_t<uint16_t, 1>(g, c, first, end, num_cu, sc, s);
+    if (orders == 2) return launch_hogwild_t<uint16_t, 2>(g, c, first, end, num_cu, sc, s);
+    return launch_hogwild_t<uint16_t, 3>(g, c, first, end, num_cu, sc, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,6 +238,176 @@ void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *b
     else
         hipLaunchKernelGGL(k_rw<uint16_t>, grid, dim3(256), 0, h->stream, (uint16_t *)h->tab[table], off, count,
                            buf, write ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 Hogwild: the binary32 shadow of the hot rows.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+// Slot of every node: nodes with heat <= hot (and a nonzero rate) take the next free slot
+// below cap, one atomic per wavefront; the others get -1.  The order of the slots is
+// immaterial: a slot only says where the row lives during the launch.
+__global__ void __launch_bounds__(256) k_shadow_slots(const uint8_t *nheat, long long n, int hot, long long cap,
+                                                      unsigned int *counter, int32_t *slot, int32_t *srows)
+{
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const unsigned hv = r < n ? (unsigned)nheat[r] : 255u;
+    const bool want = r < n && hv != 255u && (int)hv <= hot;
+    const unsigned long long mask = __ballot(want);
+    unsigned base = 0u;
+    if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(mask));
+        base = (unsigned)__shfl((int)base, leader);
+    }
+    if (r < n) {
+        int sv = -1;
+        if (want) {
+            const unsigned long long idx = (unsigned long long)base + __popcll(mask & ((1ull << lane) - 1ull));
+            if (idx < (unsigned long long)cap) {
+                sv = (int)idx;
+                srows[idx] = (int32_t)r;
+            }
+        }
+        slot[r] = sv;
+    }
+}
+
+struct ShadowDev {
+    float *shadow[3];
+    uint32_t *tab[3];  // the bfloat16 tables as 4-byte units (two values each)
+    const int32_t *srows;
+    const unsigned int *counter;
+    long long cap;
+    int d, nunits;
+    unsigned long long seed, sr_key, first;
+};
+
+// One thread per (slot, unit, table): widen the row into the shadow (even elements of the
+// row first, then the odd ones).
+__global__ void __launch_bounds__(256) k_shadow_load(ShadowDev a, long long bound)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)a.nunits;
+    const long long sl = i / per;
+    const int un = (int)(i % per);
+    const long long used = (long long)*a.counter < a.cap ? (long long)*a.counter : a.cap;
+    if (sl >= bound || sl >= used) return;
+    const long long r = a.srows[sl];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (!a.shadow[t]) continue;
+        const uint32_t w = a.tab[t][r * per + un];
+        float *sw = a.shadow[t] + sl * a.d;  // even elements, then odd ones
+        sw[un] = __uint_as_float(w << 16);
+        sw[per + un] = __uint_as_float(w & 0xffff0000u);
+    }
+}
+
+// One thread per (slot, unit, table): round the shadow row back into the table, with
+// stochastic rounding whose bits come from Philox4x64-10 keyed by (seed, sr_key) at
+// counter (first, table, row, unit / 8), 32 bits per unit.
+__global__ void __launch_bounds__(256) k_shadow_store(ShadowDev a, long long bound)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)a.nunits;
+    const long long sl = i / per;
+    const int un = (int)(i % per);
+    const long long used = (long long)*a.counter < a.cap ? (long long)*a.counter : a.cap;
+    if (sl >= bound || sl >= used) return;
+    const long long r = a.srows[sl];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (!a.shadow[t]) continue;
+        const float *sw = a.shadow[t] + sl * a.d;
+        const float2 x = make_float2(sw[un], sw[per + un]);
+        const u64x4 q = philox4x64_10(a.seed, a.sr_key, a.first, (unsigned long long)t, (unsigned long long)r,
+                                      (unsigned long long)(un / 8));
+        const int qi = (un % 8) / 2;
+        const unsigned long long wd = qi == 0 ? q.x : qi == 1 ? q.y : qi == 2 ? q.z : q.w;
+        const uint32_t rnd = (uint32_t)(wd >> (32 * (un % 2)));
+        a.tab[t][r * per + un] = f32_to_bf16_sr(x.x, rnd) | (f32_to_bf16_sr(x.y, rnd >> 16) << 16);
+    }
+}
+
+bool shadow_ctx(const lh_handle *h, ShadowCtx *o)
+{
+    if (h->p.dtype != LH_BF16 || h->p.mode != LH_HOGWILD || h->lay.shadow_cap <= 0 || !h->ws) return false;
+    o->nheat = (const uint8_t *)(h->ws + h->lay.nheat);
+    o->slot = (int32_t *)(h->ws + h->lay.slot);
+    o->srows = (int32_t *)(h->ws + h->lay.srows);
+    long long k = 0;
+    for (int t = 0; t < 3; ++t) {
+        o->tab[t] = h->tab[t];
+        o->shadow[t] = h->tab[t] ? (float *)(h->ws + h->lay.shadow) + k++ * h->lay.shadow_cap * (long long)h->p.d
+                                 : nullptr;
+    }
+    o->counter = (unsigned int *)(h->ws + h->lay.status + 128);
+    o->heat_count = h->heat_count;
+    o->n = h->n;
+    o->cap = h->lay.shadow_cap;
+    o->d = h->p.d;
+    o->seed = h->p.seed;
+    o->sr_key = (3ull << 32) | (unsigned long long)(uint32_t)h->p.graph_id;
+    return true;
+}
+
+static ShadowDev shadow_dev(const ShadowCtx &sc, unsigned long long first)
+{
+    ShadowDev a;
+    for (int t = 0; t < 3; ++t) {
+        a.shadow[t] = sc.shadow[t];
+        a.tab[t] = (uint32_t *)sc.tab[t];
+    }
+    a.srows = sc.srows;
+    a.counter = sc.counter;
+    a.cap = sc.cap;
+    a.d = sc.d;
+    a.nunits = sc.d / 2;
+    a.seed = sc.seed;
+    a.sr_key = sc.sr_key;
+    a.first = first;
+    return a;
+}
+
+// Hot nodes the shadow will hold for threshold hot (an upper bound when the heat counts
+// exceed cap at hot = 0, e.g. after an alias import: then the first cap nodes to ask get
+// a slot).  The threshold is lowered until the hot set fits.
+static long long shadow_rows(const ShadowCtx &sc, int &hot)
+{
+    if (hot > 254) hot = 254;
+    for (;;) {
+        long long c = 0;
+        for (int v = 0; v <= hot; ++v) c += (long long)sc.heat_count[v];
+        if (hot < 0) return 0;
+        if (c <= sc.cap || hot == 0) return c < sc.cap ? c : sc.cap;
+        --hot;
+    }
+}
+
+hipError_t shadow_begin(const ShadowCtx &sc, int hot_heat, hipStream_t s)
+{
+    int hot = hot_heat;
+    const long long rows = shadow_rows(sc, hot);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, sc.counter);
+    hipLaunchKernelGGL(k_shadow_slots, dim3((unsigned)LH_CDIV(sc.n, 256)), dim3(256), 0, s, sc.nheat, sc.n, hot,
+                       sc.cap, sc.counter, sc.slot, sc.srows);
+    if (rows > 0)
+        hipLaunchKernelGGL(k_shadow_load, dim3((unsigned)LH_CDIV(rows * (sc.d / 2), 256)), dim3(256), 0, s,
+                           shadow_dev(sc, 0), rows);
+    return hipGetLastError();
+}
+
+hipError_t shadow_end(const ShadowCtx &sc, int hot_heat, unsigned long long first, hipStream_t s)
+{
+    int hot = hot_heat;
+    const long long rows = shadow_rows(sc, hot);
+    if (rows > 0)
+        hipLaunchKernelGGL(k_shadow_store, dim3((unsigned)LH_CDIV(rows * (sc.d / 2), 256)), dim3(256), 0, s,
+                           shadow_dev(sc, first), rows);
+    return hipGetLastError();
 }
 
 }  // namespace lh

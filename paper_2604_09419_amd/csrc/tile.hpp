@@ -95,6 +95,8 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 // Element e of a unit as binary32.
 template <typename TT>
 __device__ __forceinline__ float val(uint32_t w, int e)
@@ -124,16 +126,39 @@ __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint
     }
 }
 
-template <typename TT, int LPS, int UPL, int KMAX>
-__device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, const TT *A, const TT *B,
-                                          int u, const int (&ids)[KMAX + 1], int K, int gl)
+// Row `id` of table t: the table row, or (bfloat16, id < 0) shadow row ~id, whose binary32
+// values are rounded to nearest even for the arithmetic.  A shadow row holds the even
+// elements of the row and then the odd ones (element 2 un + e at e * d / 2 + un), so the
+// lanes of a group touch contiguous words for each half.
+template <typename TT, int LPS, int UPL>
+__device__ __forceinline__ void load_row_of(const GraphDev &g, int t, int id, int gl, uint32_t (&o)[UPL])
 {
-    const int d = g.d, nu = g.nunits;
-    load_row<TT, LPS, UPL>(A + (long long)u * d, nu, gl, r.a);
+    if constexpr (sizeof(TT) == 2) {
+        if (id < 0) {
+            const float *sw = g.shadow[t] + (long long)(~id) * g.d;
+            const int half = g.nunits;
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                const int un = k * LPS + gl;
+                uint32_t v = 0u;
+                if (un < half) v = f32_to_bf16_rne(sw[un]) | (f32_to_bf16_rne(sw[half + un]) << 16);
+                o[k] = v;
+            }
+            return;
+        }
+    }
+    load_row<TT, LPS, UPL>((const TT *)g.tab[t] + (long long)id * g.d, g.nunits, gl, o);
+}
+
+template <typename TT, int LPS, int UPL, int KMAX>
+__device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, int tA, int tB, int u,
+                                          const int (&ids)[KMAX + 1], int K, int gl)
+{
+    load_row_of<TT, LPS, UPL>(g, tA, u, gl, r.a);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j <= K) {
-            load_row<TT, LPS, UPL>(B + (long long)ids[j] * d, nu, gl, r.b[j]);
+            load_row_of<TT, LPS, UPL>(g, tB, ids[j], gl, r.b[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < UPL; ++k) r.b[j][k] = 0u;
@@ -141,17 +166,36 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
     }
 }
 
-// Write one row back: new = old + inc.  Cold rows are stored; hot rows get atomic
-// increments (binary32) or a compare-and-swap loop of the stochastically rounded sum
-// (bfloat16, at most 64 attempts per unit, after which the unit keeps the other
-// writer's value).  The random bits of unit un are lowbias32(sr + (ctr * 256 + un) * phi).
+// Write one row back: new = old + inc.
+//   binary32: cold rows are stored, hot rows get atomic increments;
+//   bfloat16: table rows (id >= 0) are stored with stochastic rounding, the random bits
+//   of unit un being lowbias32(sr + (ctr * 256 + un) * phi); shadow rows (id < 0, even
+//   elements then odd ones) get binary32 atomic increments.
 template <typename TT, int LPS, int UPL>
-__device__ __forceinline__ void write_row(TT *row, int nunits, int gl, const uint32_t (&old)[UPL],
+__device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
                                           uint32_t ctr)
 {
     constexpr int EPU = Elem<TT>::EPU;
-    uint32_t *w = reinterpret_cast<uint32_t *>(row);
+    const int nunits = g.nunits;
+    if constexpr (EPU == 2) {
+        if (id < 0) {
+            float *sw = g.shadow[t] + (long long)(~id) * g.d;
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                const int un = k * LPS + gl;
+                if (un < nunits) atomicAdd(sw + un, inc[k][0]);
+            }
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                const int un = k * LPS + gl;
+                if (un < nunits) atomicAdd(sw + nunits + un, inc[k][1]);
+            }
+            return;
+        }
+        hot = false;
+    }
+    uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
     if (!hot) {
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
@@ -165,50 +209,24 @@ __device__ __forceinline__ void write_row(TT *row, int nunits, int gl, const uin
                 w[un] = f32_to_unit<TT>(x, rnd);
             }
         }
-    } else if constexpr (EPU == 1) {
-#pragma unroll
-        for (int k = 0; k < UPL; ++k) {
-            const int un = k * LPS + gl;
-            if (un < nunits) atomicAdd(reinterpret_cast<float *>(row) + un, inc[k][0]);
-        }
     } else {
-        uint32_t expect[UPL], rnd[UPL];
-        unsigned pending = 0u;
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const int un = k * LPS + gl;
-            rnd[k] = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
-            expect[k] = old[k];
-            if (un < nunits) pending |= 1u << k;
-        }
-        for (int attempt = 0; attempt < 64 && pending; ++attempt) {
-#pragma unroll
-            for (int k = 0; k < UPL; ++k) {
-                if (pending & (1u << k)) {
-                    float cur[2], x[2];
-                    unit_to_f32<TT>(expect[k], cur);
-                    x[0] = cur[0] + inc[k][0];
-                    x[1] = cur[1] + inc[k][1];
-                    const uint32_t want = f32_to_unit<TT>(x, rnd[k]);
-                    const uint32_t seen = atomicCAS(w + (k * LPS + gl), expect[k], want);
-                    if (seen == expect[k])
-                        pending &= ~(1u << k);
-                    else
-                        expect[k] = seen;
-                }
-            }
+            if (un < nunits) atomicAdd(reinterpret_cast<float *>(w) + un, inc[k][0]);
         }
     }
 }
 
-// One order of one sample, rows already loaded.  A holds the vertex rows, B the context
-// rows (A == B for first order).  ids[0] = v, ids[1..K] = negatives.  hot: bit 0 for
-// the vertex row, bit 1 + j for slot j.
+// One order of one sample, rows already loaded.  Table tabA holds the vertex rows, tabB
+// the context rows (the same table for first order).  ids[0] = v, ids[1..K] = negatives
+// (bfloat16 Hogwild: ~slot for rows in the shadow).  hot: bit 0 for the vertex row,
+// bit 1 + j for slot j.
 template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP>
-__device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u, const int (&ids)[KMAX + 1],
-                                          int K, float eta, unsigned dupb, unsigned dupu, unsigned hot,
-                                          uint32_t sr, int oi, int gl, const SnapOut &so, unsigned long long s,
-                                          int tabA, int tabB, const Rows<TT, UPL, KMAX> &rows)
+__device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&ids)[KMAX + 1], int K, float eta,
+                                          unsigned dupb, unsigned dupu, unsigned hot, uint32_t sr, int oi, int gl,
+                                          const SnapOut &so, unsigned long long s, int tabA, int tabB,
+                                          const Rows<TT, UPL, KMAX> &rows)
 {
     constexpr int EPU = Elem<TT>::EPU;
     const int d = g.d, nu = g.nunits;
@@ -219,9 +237,15 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
     for (int j = 0; j <= KMAX; ++j) {
         float x = 0.f;
 #pragma unroll
-        for (int k = 0; k < UPL; ++k)
-#pragma unroll
-            for (int e = 0; e < EPU; ++e) x = fmaf(val<TT>(a[k], e), val<TT>(b[j][k], e), x);
+        for (int k = 0; k < UPL; ++k) {
+            if constexpr (EPU == 2) {
+                // bfloat16 pairs: v_dot2_f32_bf16 (exact products, binary32 accumulation)
+                x = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a[k]),
+                                                    __builtin_bit_cast(bf16x2_t, b[j][k]), x, false);
+            } else {
+                x = fmaf(val<TT>(a[k], 0), val<TT>(b[j][k], 0), x);
+            }
+        }
         gj[j] = x;
     }
 #pragma unroll
@@ -336,8 +360,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
                     if (FIRST) t += GA * val<TT>(a[k], e) - cA * el * val<TT>(a[k], e);
                     inc[k][e] = t;
                 }
-            write_row<TT, LPS, UPL>(A + (long long)u * d, nu, gl, a, inc, (hot & 1u) != 0, sr,
-                                    (uint32_t)(oi * (KMAX + 2)));
+            write_row<TT, LPS, UPL>(g, tabA, u, gl, a, inc, (hot & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
         }
         // context rows
 #pragma unroll
@@ -349,7 +372,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, TT *A, TT *B, int u
             for (int k = 0; k < UPL; ++k)
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) inc[k][e] = Gm[j] * val<TT>(a[k], e) - cm[j] * el * val<TT>(b[j][k], e);
-            write_row<TT, LPS, UPL>(B + (long long)ids[j] * d, nu, gl, b[j], inc, (hot & (2u << j)) != 0, sr,
+            write_row<TT, LPS, UPL>(g, tabB, ids[j], gl, b[j], inc, (hot & (2u << j)) != 0, sr,
                                     (uint32_t)(oi * (KMAX + 2) + 1 + j));
         }
     }
@@ -428,6 +451,27 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
                 for (int jj = 0; jj < j; ++jj)
                     if (my_ids[jj] == my_ids[j]) my_dup |= 1u << j;
             }
+            // bfloat16 Hogwild: the rows with a shadow slot are this launch's hot rows; their
+            // ids become ~slot (negative, so equal rows stay equal and never meet a table id).
+            if constexpr (sizeof(TT) == 2 && !SNAP) {
+                my_hot = 0;
+                if (g.slot) {
+                    int sl[KMAX + 2];
+                    sl[0] = g.slot[my_u];
+#pragma unroll
+                    for (int j = 0; j <= KMAX; ++j) sl[j + 1] = j <= K ? g.slot[my_ids[j]] : -1;
+                    if (sl[0] >= 0) {
+                        my_u = ~sl[0];
+                        my_hot |= 1u;
+                    }
+#pragma unroll
+                    for (int j = 0; j <= KMAX; ++j)
+                        if (sl[j + 1] >= 0) {
+                            my_ids[j] = ~sl[j + 1];
+                            my_hot |= 2u << j;
+                        }
+                }
+            }
         }
     }
 
@@ -451,19 +495,18 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
         // 2 (2 + K) rows per sample are in flight at once.
         Rows<TT, UPL, KMAX> r2, r1;
         if constexpr ((ORD & 2) != 0)
-            load_rows<TT, LPS, UPL, KMAX>(r2, g, (const TT *)g.tab[0], (const TT *)g.tab[1], u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX>(r2, g, LH_TABLE_U, LH_TABLE_C, u, ids, K, gl);
         if constexpr ((ORD & 1) != 0)
-            load_rows<TT, LPS, UPL, KMAX>(r1, g, (const TT *)g.tab[2], (const TT *)g.tab[2], u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX>(r1, g, LH_TABLE_U1, LH_TABLE_U1, u, ids, K, gl);
         int oi = 0;
         if constexpr ((ORD & 2) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, false, SNAP>(g, (TT *)g.tab[0], (TT *)g.tab[1], u, ids, K, eta, dupb,
-                                                       dupu, hot, sr, oi, gl, so, s, LH_TABLE_U, LH_TABLE_C, r2);
+            sgd_order<TT, LPS, UPL, KMAX, false, SNAP>(g, u, ids, K, eta, dupb, dupu, hot, sr, oi, gl, so, s,
+                                                       LH_TABLE_U, LH_TABLE_C, r2);
             ++oi;
         }
         if constexpr ((ORD & 1) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, true, SNAP>(g, (TT *)g.tab[2], (TT *)g.tab[2], u, ids, K, eta, dupb,
-                                                      dupu, hot, sr ^ 0x5bd1e995u, oi, gl, so, s, LH_TABLE_U1,
-                                                      LH_TABLE_U1, r1);
+            sgd_order<TT, LPS, UPL, KMAX, true, SNAP>(g, u, ids, K, eta, dupb, dupu, hot, sr ^ 0x5bd1e995u, oi, gl,
+                                                      so, s, LH_TABLE_U1, LH_TABLE_U1, r1);
         }
     }
 }
