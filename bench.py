@@ -79,7 +79,7 @@ def measured_traffic(path: str, kernel_config: dict, total_samples: int):
     try:
         cfg = [int(x) for x in rec["kernel_config"].split()]
         ok = (rec["kernel_sources_sha256"] == kernel_sources_sha256()
-              and cfg == [kernel_config["lanes_per_sample"], kernel_config["chunks_per_lane"],
+              and cfg == [kernel_config["lanes_per_sample"], kernel_config["units_per_lane"],
                           kernel_config["blocks_per_cu"]]
               and int(rec["total_samples"]) == int(total_samples))
         return float(rec["traffic_bytes_per_launch"]) if ok else None

@@ -150,16 +150,23 @@ LH_API lh_status lh_sample(lh_handle *h, uint64_t first, uint64_t count, int32_t
  * SNAPSHOT needs first % batch == 0 and processes batches [bB, min((b+1)B, end)). */
 LH_API lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count);
 
-/* Pick the Hogwild kernel configuration (lanes per sample, 16-byte chunks per lane,
+/* Pick the Hogwild kernel configuration (lanes per sample, 4-byte units per lane,
  * workgroups per compute unit) for this handle's shape by timing each candidate on
  * samples [0, probe) with the step size scaled to zero, so the tables are left as they
  * were.  cache_path (may be NULL) names a JSON file of earlier choices keyed by device,
  * dtype, d, K and orders; a hit skips the timing.  Synchronises. */
 LH_API lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_path);
 
-/* The Hogwild kernel configuration in use: out[0] lanes per sample, out[1] 16-byte chunks
- * per lane, out[2] workgroups per compute unit (host memory, 3 int32). */
+/* The Hogwild kernel configuration in use: out[0] lanes per sample, out[1] 4-byte units
+ * of a row per lane (one binary32 value or two bfloat16 values each), out[2] workgroups
+ * per compute unit (host memory, 3 int32). */
 LH_API lh_status lh_kernel_config(const lh_handle *h, int32_t out[3]);
+
+/* Use configuration cfg (same layout as lh_kernel_config's out) for later Hogwild
+ * launches, e.g. one found by the caller's own timing.  (lanes, units) must be one of
+ * (16|32|64, 1 or 2), (2..64, 4), (4..64, 8) with lanes x units >= the row's units, and
+ * 1 <= workgroups <= 64; else LH_ERR_INVALID_ARG and the configuration is unchanged. */
+LH_API lh_status lh_set_kernel_config(lh_handle *h, const int32_t cfg[3]);
 
 /* Copy rows [row0, row0 + rows) of table t (LH_TABLE_*) to / from a binary32 device
  * buffer [rows x d]; bfloat16 tables convert (reads exactly, writes round to nearest even). */
@@ -189,8 +196,7 @@ LH_API lh_status lh_destroy(lh_handle *h);
  * cache_path (may be NULL) names a JSON file of earlier choices keyed by device and shape.
  * The batch object owns two small device buffers (the graph descriptors and the work
  * counters) and the hipGraph; lh_batch_destroy frees them.  It supports second-order
- * HOGWILD handles of one dtype with rows of at most 16 (bfloat16) or 32 (binary32)
- * 16-byte chunks; other mixes return LH_ERR_UNSUPPORTED. */
+ * HOGWILD handles of one dtype with d <= 128; other mixes return LH_ERR_UNSUPPORTED. */
 LH_API lh_status lh_batch_create(lh_batch **b, int G, lh_handle *const *graphs);
 LH_API lh_status lh_batch_tune(lh_batch *b, const char *cache_path);
 LH_API lh_status lh_batch_capture(lh_batch *b);

@@ -131,6 +131,9 @@ class Trainer:
     def kernel_config(self):
         return _lib.lh_kernel_config(self.h)
 
+    def set_kernel_config(self, lanes_per_sample: int, units_per_lane: int, blocks_per_cu: int):
+        _lib.lh_set_kernel_config(self.h, lanes_per_sample, units_per_lane, blocks_per_cu)
+
     def read(self, table: int, row0: int = 0, rows: Optional[int] = None):
         """Rows of table ``table`` as a float32 tensor on the GPU (bfloat16 widened)."""
         torch = self.torch

@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         "lh_check": [P],
         "lh_last_train_ms": [P, ctypes.POINTER(ctypes.c_double)],
         "lh_kernel_config": [P, ctypes.POINTER(ctypes.c_int32 * 3)],
+        "lh_set_kernel_config": [P, ctypes.POINTER(ctypes.c_int32 * 3)],
         "lh_destroy": [P],
         "lh_batch_create": [PP, S, ctypes.POINTER(ctypes.c_void_p)],
         "lh_batch_tune": [P, ctypes.c_char_p],
@@ -196,7 +197,12 @@ def lh_last_train_ms(h) -> float:
 def lh_kernel_config(h):
     out = (ctypes.c_int32 * 3)()
     check(lib().lh_kernel_config(h, ctypes.byref(out)), "lh_kernel_config", h)
-    return {"lanes_per_sample": out[0], "chunks_per_lane": out[1], "blocks_per_cu": out[2]}
+    return {"lanes_per_sample": out[0], "units_per_lane": out[1], "blocks_per_cu": out[2]}
+
+
+def lh_set_kernel_config(h, lanes_per_sample: int, units_per_lane: int, blocks_per_cu: int):
+    arr = (ctypes.c_int32 * 3)(lanes_per_sample, units_per_lane, blocks_per_cu)
+    check(lib().lh_set_kernel_config(h, ctypes.byref(arr)), "lh_set_kernel_config", h)
 
 
 def lh_destroy(h):

@@ -36,7 +36,6 @@ GraphDev graph_dev(const lh_handle *h)
     g.alpha = (float)h->p.alpha_neg;
     g.eta_scale = 1.0f;
     g.d = h->p.d;
-    g.nch = h->p.d / (h->p.dtype == LH_FP32 ? 4 : 8);
     g.nunits = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;
     g.K = h->p.K;
     g.hot_heat = -1;
@@ -116,7 +115,7 @@ using namespace lh;
 static const char *const kSymbols[] = {
     "lh_create",          "lh_workspace_size", "lh_bind",          "lh_set_graph",       "lh_build_alias",
     "lh_import_alias",    "lh_export_alias",   "lh_init_embeddings", "lh_sample",        "lh_train_steps",
-    "lh_read_embeddings", "lh_write_embeddings", "lh_check",       "lh_last_train_ms",   "lh_tune",   "lh_kernel_config",
+    "lh_read_embeddings", "lh_write_embeddings", "lh_check",       "lh_last_train_ms",   "lh_tune",   "lh_kernel_config", "lh_set_kernel_config",
     "lh_status_string",   "lh_last_error",     "lh_destroy",       "lh_batch_create",    "lh_batch_tune",
     "lh_batch_capture",   "lh_batch_launch",   "lh_batch_run",     "lh_batch_last_ms",   "lh_batch_done",      "lh_batch_destroy",
     "lh_abi_symbol_count", "lh_abi_symbol_name",
@@ -322,11 +321,24 @@ lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count)
     return LH_OK;
 }
 
+lh_status lh_set_kernel_config(lh_handle *h, const int32_t cfg[3])
+{
+    if (!h || !cfg) return LH_ERR_INVALID_ARG;
+    TileCfg c;
+    c.lps = cfg[0];
+    c.upl = cfg[1];
+    c.blocks_per_cu = cfg[2];
+    if (!cfg_supported(h->p.dtype, h->p.d, c))
+        return fail(h, LH_ERR_INVALID_ARG, "no kernel for this (lanes, units, workgroups) at this width");
+    h->cfg = c;
+    return LH_OK;
+}
+
 lh_status lh_kernel_config(const lh_handle *h, int32_t out[3])
 {
     if (!h || !out) return LH_ERR_INVALID_ARG;
     out[0] = h->cfg.lps;
-    out[1] = h->cfg.cpl;
+    out[1] = h->cfg.upl;
     out[2] = h->cfg.blocks_per_cu;
     return LH_OK;
 }

@@ -104,21 +104,20 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     (void)hipGetDevice(&dev);
     if (dev != h->device) (void)hipSetDevice(h->device);
     char key[160];
-    std::snprintf(key, sizeof(key), "%s|hogwild|dt%d|d%d|K%d|o%d|n%d", arch_name(h->device).c_str(), h->p.dtype,
+    std::snprintf(key, sizeof(key), "%s|hogwild-upl|dt%d|d%d|K%d|o%d|n%d", arch_name(h->device).c_str(), h->p.dtype,
                   h->p.d, h->p.K, h->p.orders, log2_bucket(h->n));
     int hit[4];
     if (cache_lookup(cache_path, key, hit)) {
         TileCfg c;
         c.lps = hit[0];
-        c.cpl = hit[1];
+        c.upl = hit[1];
         c.blocks_per_cu = hit[2];
         if (cfg_supported(h->p.dtype, h->p.d, c)) {
             h->cfg = c;
             return LH_OK;
         }
     }
-    const int vec = h->p.dtype == LH_FP32 ? 4 : 8;
-    const int nch = h->p.d / vec;
+    const int nu = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;
     GraphDev g = graph_dev(h);
     g.eta_scale = 0.0f;  // dry run: every row is written back unchanged
     const int lps_opts[] = {2, 4, 8, 16, 32, 64};
@@ -127,12 +126,12 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LH_ERR_HIP;
-    for (int cpl = 1; cpl <= 2; ++cpl) {
+    for (int upl : {2, 4, 8}) {
         for (int lps : lps_opts) {
             TileCfg c;
             c.lps = lps;
-            c.cpl = cpl;
-            if (lps * cpl < nch || (lps * cpl >= 2 * nch && lps > 2)) continue;
+            c.upl = upl;
+            if (lps * upl < nu || (lps * upl >= 2 * nu && lps > 2)) continue;
             for (int bpc : bpc_opts) {
                 c.blocks_per_cu = bpc;
                 if (!cfg_supported(h->p.dtype, h->p.d, c)) continue;
@@ -156,7 +155,7 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->cfg = best;
-    int v[4] = {best.lps, best.cpl, best.blocks_per_cu, 0};
+    int v[4] = {best.lps, best.upl, best.blocks_per_cu, 0};
     cache_store(cache_path, key, v);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LH_OK : hip_fail(h, e, "tune");
@@ -188,25 +187,27 @@ struct BatchArgs {
     unsigned long long *done;  // [G]
 };
 
-// Tile configurations by variant: 0 = natural lanes per sample, 1 = half the lanes with
-// two chunks each.  SMALL serves rows of at most NCH_SMALL chunks, LARGE the rest.
+// Tile configurations by variant (lanes per sample, units per lane).  Binary32: 0 = four
+// units per lane, 1 = half the lanes with eight units each.  bfloat16: 0 = one unit per
+// lane (the fastest single-graph shape), 1 = four units per lane.  The small tile serves
+// rows of at most LS * US units, the large one the rest.
 template <typename TT, int V>
 struct BatchCfg;
 template <>
 struct BatchCfg<uint16_t, 0> {
-    static constexpr int LS = 8, CS = 1, LL = 16, CL = 1;
+    static constexpr int LS = 32, US = 1, LL = 64, UL = 1;
 };
 template <>
 struct BatchCfg<uint16_t, 1> {
-    static constexpr int LS = 4, CS = 2, LL = 8, CL = 2;
+    static constexpr int LS = 8, US = 4, LL = 16, UL = 4;
 };
 template <>
 struct BatchCfg<float, 0> {
-    static constexpr int LS = 16, CS = 1, LL = 32, CL = 1;
+    static constexpr int LS = 16, US = 4, LL = 32, UL = 4;
 };
 template <>
 struct BatchCfg<float, 1> {
-    static constexpr int LS = 8, CS = 2, LL = 16, CL = 2;
+    static constexpr int LS = 8, US = 8, LL = 16, UL = 8;
 };
 
 __global__ void k_batch_reset(unsigned long long *queue, unsigned long long *done, int G)
@@ -236,12 +237,12 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a)
         unsigned long long s0 = chunk * a.item_samples;
         unsigned long long s1 = s0 + a.item_samples;
         if (s1 > D.limit) s1 = D.limit;
-        if (g.nch <= Cfg::LS * Cfg::CS) {
+        if (g.nunits <= Cfg::LS * Cfg::US) {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LS, 4 * Cfg::CS, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LS, Cfg::US, KMAX, 2, false>(g, t, s1, so);
         } else {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LL, 4 * Cfg::CL, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LL, Cfg::UL, KMAX, 2, false>(g, t, s1, so);
         }
         if (lane == 0 && s1 > s0) atomicAdd(&a.done[lo], s1 - s0);
     }
@@ -427,10 +428,8 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
         if (h->p.mode != LH_HOGWILD || h->p.orders != LH_ORDER2) return LH_ERR_UNSUPPORTED;
         if (h->p.dtype != graphs[0]->p.dtype || h->device != graphs[0]->device) return LH_ERR_UNSUPPORTED;
         if ((h->p.K <= 5) != (graphs[0]->p.K <= 5)) return LH_ERR_UNSUPPORTED;
-        const int vec = h->p.dtype == LH_FP32 ? 4 : 8;
-        const int nch = h->p.d / vec;
-        const int cap = h->p.dtype == LH_FP32 ? 32 : 16;
-        if (nch > cap) return LH_ERR_UNSUPPORTED;
+        const int nu = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;  // 4-byte units per row
+        if (nu > (h->p.dtype == LH_FP32 ? 128 : 64)) return LH_ERR_UNSUPPORTED;
     }
     lh_batch *b = new (std::nothrow) lh_batch();
     if (!b) return LH_ERR_HIP;

@@ -20,7 +20,7 @@ struct GraphDev {
     double eta0;
     float lambda, alpha;
     float eta_scale;           // 1 for training, 0 for timing-only dry runs
-    int d, nch;                // width and number of 16-byte chunks per row
+    int d;                     // width
     int nunits;                // 4-byte units per row (d binary32 values or d/2 bfloat16 pairs)
     int K;
     int hot_heat;              // rows with heat <= hot_heat take atomic increments (-1: none)
@@ -34,9 +34,10 @@ struct GraphDev {
     const int32_t *slot;
 };
 
-// A kernel configuration: lanes per sample and 16-byte chunks per lane.
+// A kernel configuration: lanes per sample, 4-byte units of a row per lane (a unit is one
+// binary32 value or two bfloat16 values) and workgroups per compute unit.
 struct TileCfg {
-    int lps = 0, cpl = 0, blocks_per_cu = 0;
+    int lps = 0, upl = 0, blocks_per_cu = 0;
 };
 
 struct WsLayout {
@@ -56,7 +57,11 @@ struct ScratchLayout {
 
 WsLayout ws_layout(const lh_params &p, long long n, long long m);
 
-// Shadow rows per table of a bfloat16 Hogwild handle with n nodes: every node of a graph
+// bfloat16 Hogwild handles keep their hot rows in a binary32 shadow.  (Binary32 handles
+// apply their atomics to the table rows: a compact shadow measured no faster for them.)
+inline bool uses_shadow(int dtype, int mode) { return mode == LH_HOGWILD && dtype == LH_BF16; }
+
+// Shadow rows per table of a Hogwild handle with a shadow and n nodes: every node of a graph
 // of up to 2^17 nodes, else one node in 16.  The hot set of a launch is trimmed to fit.
 inline long long shadow_capacity(long long n)
 {
@@ -140,6 +145,7 @@ void launch_sample(lh_handle *h, unsigned long long first, unsigned long long co
                    int32_t *v, int32_t *neg);
 void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *buf, bool write);
 TileCfg default_cfg(int dtype, int d);
+TileCfg natural_cfg(int dtype, int d);
 bool cfg_supported(int dtype, int d, const TileCfg &c);
 hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c,
                           unsigned long long first, unsigned long long end, int num_cu,

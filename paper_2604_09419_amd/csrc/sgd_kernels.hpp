@@ -10,11 +10,14 @@
 
 namespace lh {
 
-// Grid-stride over 64-sample tiles: wave w takes tiles w, w + W, w + 2W, ...  The kernel
-// is latency bound, so the register budget is capped for at least 3 waves per SIMD
-// (measured: bfloat16 rows otherwise take 232 VGPRs, 2 waves, and run 18 % slower).
-template <typename TT, int LPS, int CPL, int KMAX, int ORD>
-__global__ void __launch_bounds__(256, 3) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)
+// Grid-stride over 64-sample tiles: wave w takes tiles w, w + W, w + 2W, ...  The register
+// budget is capped for at least 3 (binary32) or 4 (bfloat16) waves per SIMD: the
+// bfloat16 kernel is latency bound and measured fastest there, a few spills included.
+template <typename TT>
+constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 4 : 3; }
+
+template <typename TT, int LPS, int UPL, int KMAX, int ORD>
+__global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)
 {
     const unsigned wpb = blockDim.x >> 6;
     unsigned long long wave = (unsigned long long)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -22,10 +25,10 @@ __global__ void __launch_bounds__(256, 3) k_hogwild(GraphDev g, unsigned long lo
     unsigned long long ntiles = (end - first + 63) / 64;
     SnapOut so{};
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, 4 * CPL, KMAX, ORD, false>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, UPL, KMAX, ORD, false>(g, first + t * 64, end, so);
 }
 
-template <typename TT, int LPS, int CPL, int KMAX, int ORD>
+template <typename TT, int LPS, int UPL, int KMAX, int ORD>
 __global__ void __launch_bounds__(256) k_snap_contrib(GraphDev g, unsigned long long first, unsigned long long end,
                                                       SnapOut so)
 {
@@ -34,7 +37,7 @@ __global__ void __launch_bounds__(256) k_snap_contrib(GraphDev g, unsigned long 
     unsigned long long nw = (unsigned long long)gridDim.x * wpb;
     unsigned long long ntiles = (end - first + 63) / 64;
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, 4 * CPL, KMAX, ORD, true>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, UPL, KMAX, ORD, true>(g, first + t * 64, end, so);
 }
 
 inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_per_cu)
@@ -73,28 +76,35 @@ inline double samples_in_flight(KernelT kernel, unsigned grid, int num_cu, int l
     return blocks * 4.0 * (64.0 / lps);
 }
 
+// (lanes per sample, units per lane) of the Hogwild kernels.
 #define LH_CFG_LIST(X) \
-    X(2, 1)            \
-    X(4, 1)            \
-    X(8, 1)            \
     X(16, 1)           \
     X(32, 1)           \
     X(64, 1)           \
-    X(4, 2)            \
-    X(8, 2)            \
     X(16, 2)           \
     X(32, 2)           \
-    X(64, 2)
+    X(64, 2)           \
+    X(2, 4)            \
+    X(4, 4)            \
+    X(8, 4)            \
+    X(16, 4)           \
+    X(32, 4)           \
+    X(64, 4)           \
+    X(4, 8)            \
+    X(8, 8)            \
+    X(16, 8)           \
+    X(32, 8)           \
+    X(64, 8)
 
 // SNAPSHOT contributions use only the natural configuration of each width.
 #define LH_SNAP_CFG_LIST(X) \
-    X(2, 1)                 \
-    X(4, 1)                 \
-    X(8, 1)                 \
-    X(16, 1)                \
-    X(32, 1)                \
-    X(64, 1)                \
-    X(64, 2)
+    X(2, 4)                 \
+    X(4, 4)                 \
+    X(8, 4)                 \
+    X(16, 4)                \
+    X(32, 4)                \
+    X(64, 4)                \
+    X(64, 8)
 
 // One Hogwild launch: the grid of the configuration, lowered if the graph's staleness
 // cap asks for fewer samples in flight, and the heat threshold for that concurrency.
@@ -131,7 +141,7 @@ hipError_t launch_hogwild_t(const GraphDev &g, const TileCfg &c, unsigned long l
 {
     const bool k5 = g.K <= 5;
 #define LH_LAUNCH_H(L, C)                                                 \
-    if (c.lps == L && c.cpl == C) {                                       \
+    if (c.lps == L && c.upl == C) {                                       \
         if (k5)                                                           \
             return launch_one(k_hogwild<TT, L, C, 5, ORD>, L, g, c, first, end, num_cu, sc, s); \
         return launch_one(k_hogwild<TT, L, C, 8, ORD>, L, g, c, first, end, num_cu, sc, s);     \
@@ -148,7 +158,7 @@ hipError_t launch_snap_t(const GraphDev &g, const TileCfg &c, unsigned long long
     const bool k5 = g.K <= 5;
     dim3 grid(hogwild_grid(end - first, num_cu, 8)), block(256);
 #define LH_LAUNCH_S(L, C)                                                                              \
-    if (c.lps == L && c.cpl == C) {                                                                    \
+    if (c.lps == L && c.upl == C) {                                                                    \
         if (k5)                                                                                        \
             hipLaunchKernelGGL((k_snap_contrib<TT, L, C, 5, ORD>), grid, block, 0, s, g, first, end, so); \
         else                                                                                           \

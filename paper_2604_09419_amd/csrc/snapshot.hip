@@ -172,7 +172,7 @@ lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long l
     int bits = 1;
     while (bits < 32 && (1ull << bits) < 3ull * (unsigned long long)h->n) ++bits;
     const int passes = (bits + 3) / 4;
-    TileCfg c = default_cfg(p.dtype, p.d);
+    TileCfg c = natural_cfg(p.dtype, p.d);
     const int apply_lps = c.lps;
 
     const unsigned long long end = first + count;

@@ -96,6 +96,7 @@ __device__ __forceinline__ float group_sum(float x)
 }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef short short2_t __attribute__((ext_vector_type(2)));
 
 // Element e of a unit as binary32.
 template <typename TT>
@@ -166,11 +167,12 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
     }
 }
 
-// Write one row back: new = old + inc.
-//   binary32: cold rows are stored, hot rows get atomic increments;
+// Write one row back: new = old + inc.  `hot` asks for the atomic path.
+//   binary32: stored, or atomic increments;
 //   bfloat16: table rows (id >= 0) are stored with stochastic rounding, the random bits
-//   of unit un being lowbias32(sr + (ctr * 256 + un) * phi); shadow rows (id < 0, even
-//   elements then odd ones) get binary32 atomic increments.
+//   of unit un being lowbias32(sr + (ctr * 256 + un) * phi), or (hot: a row repeated
+//   within the sample) get packed bfloat16 atomic adds; shadow rows (id < 0, even
+//   elements then odd ones) always get binary32 atomic increments.
 template <typename TT, int LPS, int UPL>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
@@ -193,7 +195,22 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
             }
             return;
         }
-        hot = false;
+        if (hot) {
+            // a table row repeated within the sample: packed bfloat16 atomic adds of the
+            // increments rounded to nearest even
+            uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                const int un = k * LPS + gl;
+                if (un < nunits) {
+                    const uint32_t p = f32_to_bf16_rne(inc[k][0]) | (f32_to_bf16_rne(inc[k][1]) << 16);
+                    __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                        (short2_t __attribute__((address_space(1))) *)(w + un),
+                        __builtin_bit_cast(short2_t, p));
+                }
+            }
+            return;
+        }
     }
     uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
     if (!hot) {
@@ -309,70 +326,24 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         }
         return;
     } else {
-        // Merge repeated rows: slot j's total step is Gm[j] (sum of the g of all slots
-        // with that row) and cm[j] (their number, for the decay); slots that repeat an
-        // earlier row (or, in first order, the vertex row u) write nothing.
-        float Gm[KMAX + 1], cm[KMAX + 1];
-        float GA = 0.f, cA = 0.f;
-        unsigned skip = 0;
-#pragma unroll
-        for (int j = 0; j <= KMAX; ++j) {
-            Gm[j] = gj[j];
-            cm[j] = j <= K ? 1.f : 0.f;
-        }
-        if (dupb | (FIRST ? dupu : 0u)) {
-#pragma unroll
-            for (int j = 0; j <= KMAX; ++j) {
-                if (j > K) break;
-                if (FIRST && ids[j] == u) {
-                    GA += gj[j];
-                    cA += 1.f;
-                    Gm[j] = 0.f;
-                    cm[j] = 0.f;
-                    skip |= 1u << j;
-                    continue;
-                }
-                int own = j;
-#pragma unroll
-                for (int jj = KMAX; jj >= 0; --jj)
-                    if (jj < j && ids[jj] == ids[j]) own = jj;
-                if (own != j) {
-#pragma unroll
-                    for (int jj = 0; jj <= KMAX; ++jj)
-                        if (jj == own) {
-                            Gm[jj] += gj[j];
-                            cm[jj] += 1.f;
-                        }
-                    Gm[j] = 0.f;
-                    cm[j] = 0.f;
-                    skip |= 1u << j;
-                }
-            }
-        }
+        // A row that occurs more than once in this order of the sample (two slots with
+        // one row, or in first order a slot equal to the vertex row) takes the atomic
+        // path at every occurrence: each occurrence adds its own increment, computed from
+        // the rows as they were before the sample, so the row receives their sum.
+        unsigned atom = hot | (dupb << 1);
+        if constexpr (FIRST) atom |= (dupu << 1) | (dupu ? 1u : 0u);
         // vertex row
-        {
-            float inc[UPL][EPU];
-#pragma unroll
-            for (int k = 0; k < UPL; ++k)
-#pragma unroll
-                for (int e = 0; e < EPU; ++e) {
-                    float t = dA[k][e];
-                    if (FIRST) t += GA * val<TT>(a[k], e) - cA * el * val<TT>(a[k], e);
-                    inc[k][e] = t;
-                }
-            write_row<TT, LPS, UPL>(g, tabA, u, gl, a, inc, (hot & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
-        }
+        write_row<TT, LPS, UPL>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
             if (j > K) break;
-            if (skip & (1u << j)) continue;
             float inc[UPL][EPU];
 #pragma unroll
             for (int k = 0; k < UPL; ++k)
 #pragma unroll
-                for (int e = 0; e < EPU; ++e) inc[k][e] = Gm[j] * val<TT>(a[k], e) - cm[j] * el * val<TT>(b[j][k], e);
-            write_row<TT, LPS, UPL>(g, tabB, ids[j], gl, b[j], inc, (hot & (2u << j)) != 0, sr,
+                for (int e = 0; e < EPU; ++e) inc[k][e] = gj[j] * val<TT>(a[k], e) - el * val<TT>(b[j][k], e);
+            write_row<TT, LPS, UPL>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0, sr,
                                     (uint32_t)(oi * (KMAX + 2) + 1 + j));
         }
     }
@@ -442,14 +413,15 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
                     if (g.hot_heat >= 0 && hn <= hh) my_hot |= 4u << j;
                 }
             }
-            // repeated rows among (v, n_1..n_K) in the low half, rows equal to u in the high half
+            // low half: slots whose row occurs in another slot too (every occurrence);
+            // high half: slots whose row is the vertex row u
 #pragma unroll
             for (int j = 0; j <= KMAX; ++j) {
                 if (j > K) break;
                 if (my_ids[j] == my_u) my_dup |= 1u << (16 + j);
 #pragma unroll
                 for (int jj = 0; jj < j; ++jj)
-                    if (my_ids[jj] == my_ids[j]) my_dup |= 1u << j;
+                    if (my_ids[jj] == my_ids[j]) my_dup |= (1u << j) | (1u << jj);
             }
             // bfloat16 Hogwild: the rows with a shadow slot are this launch's hot rows; their
             // ids become ~slot (negative, so equal rows stay equal and never meet a table id).

@@ -23,7 +23,7 @@ def test_algorithmic_bytes_per_sample():
     assert bench.algorithmic_bytes_per_sample(128, 5, 2, 2) == 2 * 7 * 256 + 32 + 80
 
 
-def _summary(tmp_path, sha, cfg="32 1 16", T=200000000):
+def _summary(tmp_path, sha, cfg="32 4 16", T=200000000):
     p = tmp_path / "s.md"
     p.write_text("# x\n\n    traffic_bytes_per_launch: 123456\n"
                  f"    kernel_config: {cfg}\n    total_samples: {T}\n    kernel_sources_sha256: {sha}\n")
@@ -31,11 +31,11 @@ def _summary(tmp_path, sha, cfg="32 1 16", T=200000000):
 
 
 def test_traffic_only_for_the_measured_kernel(tmp_path):
-    cfg = {"lanes_per_sample": 32, "chunks_per_lane": 1, "blocks_per_cu": 16}
+    cfg = {"lanes_per_sample": 32, "units_per_lane": 4, "blocks_per_cu": 16}
     sha = bench.kernel_sources_sha256()
     assert bench.measured_traffic(_summary(tmp_path, sha), cfg, 200000000) == 123456.0
     assert bench.measured_traffic(_summary(tmp_path, "0" * 64), cfg, 200000000) is None
-    assert bench.measured_traffic(_summary(tmp_path, sha, cfg="16 1 16"), cfg, 200000000) is None
+    assert bench.measured_traffic(_summary(tmp_path, sha, cfg="16 4 16"), cfg, 200000000) is None
     assert bench.measured_traffic(_summary(tmp_path, sha, T=5), cfg, 200000000) is None
     assert bench.measured_traffic(str(tmp_path / "missing.md"), cfg, 200000000) is None
 

@@ -83,7 +83,7 @@ def test_tune_is_a_dry_run():
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
     cfg = tr.kernel_config()
-    assert cfg["lanes_per_sample"] * cfg["chunks_per_lane"] * 4 >= 128
+    assert cfg["lanes_per_sample"] * cfg["units_per_lane"] >= 128
 
 
 def test_tune_of_bf16_tables_is_switched_off():
