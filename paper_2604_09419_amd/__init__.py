@@ -56,6 +56,8 @@ class Trainer:
                                   batch=batch, hot_rate=hot_rate, max_conflicts=max_conflicts)
         self.h = _lib.lh_create(self.params, device)
         tdt = torch.float32 if dtype == "fp32" else torch.bfloat16
+        # Inputs given as GPU tensors may still be in the making on the caller's stream.
+        self._after_caller()
         with torch.cuda.stream(self.stream):
             self.src = torch.as_tensor(src, dtype=torch.int32).to(self.device).contiguous()
             self.dst = torch.as_tensor(dst, dtype=torch.int32).to(self.device).contiguous()
@@ -78,6 +80,11 @@ class Trainer:
         if init:
             self.init_embeddings()
 
+    def _after_caller(self):
+        """Order this trainer's stream after the caller's current stream (work the caller
+        queued there, such as producing an input tensor, finishes first)."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
     # -- the C calls ---------------------------------------------------------------------
     def build_alias(self):
         torch = self.torch
@@ -91,6 +98,7 @@ class Trainer:
 
     def import_alias(self, which: int, thr, alias):
         torch = self.torch
+        self._after_caller()
         with torch.cuda.stream(self.stream):
             t = torch.as_tensor(thr.view("int64") if hasattr(thr, "view") and not torch.is_tensor(thr) else thr)
             t = t.to(self.device, torch.int64).contiguous()
@@ -146,6 +154,7 @@ class Trainer:
 
     def write(self, table: int, x, row0: int = 0):
         torch = self.torch
+        self._after_caller()
         with torch.cuda.stream(self.stream):
             xt = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
         _lib.lh_write_embeddings(self.h, table, row0, xt.shape[0], xt.data_ptr())

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import config_graph
+from synth import config_graph, rmat_graph
 from synth.graphs import Graph
 
 from gpu_util import dot_rows, fro_rel_err, max_row_rel_err, trainer_for
@@ -331,3 +331,27 @@ def test_state_and_range_errors(c1_graph, c1_tables):
     with pytest.raises(lh.LhError) as e:
         s.train_steps(50, 100)
     assert e.value.status == 1
+
+
+def test_gpu_inputs_made_on_the_callers_stream_are_waited_for():
+    """Arcs produced on the caller's current stream behind a long queue of work are passed
+    straight to a Trainer (which works on its own stream): the library's stream must wait
+    for them, so validation passes and the alias tables equal those built from the same
+    arcs given as host arrays."""
+    import torch
+    lh = _lh()
+    g = rmat_graph(14, 12_000, 150_000, seed=31)
+    dev = torch.device("cuda", 0)
+    x = torch.randn(4096, 4096, device=dev)
+    for _ in range(20):  # queue a few tens of ms of work ahead of the arcs
+        x = torch.tanh(x @ x)
+    zero = (x[0, 0] * 0).to(torch.int32)  # depends on that work
+    src = torch.as_tensor(g.src, device=dev) + zero
+    dst = torch.as_tensor(g.dst, device=dev) + zero
+    w = torch.as_tensor(g.w, device=dev) + zero.float()
+    tr = lh.Trainer(g.n, src, dst, w, d=16, K=5, orders=2, seed=3, total_samples=1000)
+    ref = trainer_for(g, d=16, K=5, orders=2, seed=3, total_samples=1000)
+    for which in (lh.LH_ALIAS_EDGE, lh.LH_ALIAS_NEG):
+        t1, a1 = tr.export_alias(which)
+        t2, a2 = ref.export_alias(which)
+        assert np.array_equal(t1, t2) and np.array_equal(a1, a2)
