@@ -218,7 +218,7 @@ __global__ void k_batch_reset(unsigned long long *queue, unsigned long long *don
 }
 
 template <typename TT, int KMAX, int V>
-__global__ void __launch_bounds__(256) k_batch(BatchArgs a)
+__global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_batch(BatchArgs a)
 {
     using Cfg = BatchCfg<TT, V>;
     const int lane = threadIdx.x & 63;
