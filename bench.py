@@ -45,19 +45,27 @@ def algorithmic_bytes_per_sample(d: int, K: int, orders: int, elem_bytes: int) -
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_hogwild_c2_fp32_hbm_traffic.md")
 
 
-def kernel_sources_sha256() -> str:
-    """Hash of every source the library's kernels are built from: the HIP sources and
-    headers, the C header and the build script."""
-    import glob
+# The sources the C2 Hogwild training kernel and its launch are built from: the tile and
+# launch code, the handle and alias build (the hot-row thresholds), the binary32
+# orders-1+2 translation unit, the C header and the build flags.  The batched and
+# SNAPSHOT sources and the other dtype/order units do not enter this kernel.
+KERNEL_SOURCES = [
+    "paper_2604_09419_amd/csrc/common.hpp", "paper_2604_09419_amd/csrc/handle.hpp",
+    "paper_2604_09419_amd/csrc/scan.hpp", "paper_2604_09419_amd/csrc/tile.hpp",
+    "paper_2604_09419_amd/csrc/sgd_kernels.hpp", "paper_2604_09419_amd/csrc/alias.hip",
+    "paper_2604_09419_amd/csrc/api.hip", "paper_2604_09419_amd/csrc/misc.hip",
+    "paper_2604_09419_amd/csrc/sgd_f32_o3.hip", "include/linehip.h", "paper_2604_09419_amd/build.py",
+]
+
+
+def kernel_sources_sha256(root: str = ROOT) -> str:
+    """SHA-256 over KERNEL_SOURCES (path, NUL, contents, NUL each)."""
     import hashlib
-    pkg = os.path.join(ROOT, "paper_2604_09419_amd")
-    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*.hip")) + glob.glob(os.path.join(pkg, "csrc", "*.hpp")))
-    files += [os.path.join(ROOT, "include", "linehip.h"), os.path.join(pkg, "build.py")]
     h = hashlib.sha256()
-    for f in files:
-        h.update(os.path.relpath(f, ROOT).encode())
+    for rel in KERNEL_SOURCES:
+        h.update(rel.encode())
         h.update(b"\0")
-        with open(f, "rb") as fh:
+        with open(os.path.join(root, rel), "rb") as fh:
             h.update(fh.read())
         h.update(b"\0")
     return h.hexdigest()
