@@ -83,6 +83,9 @@ def test_null_handles_rejected(L):
     assert L.lh_check(None) == 1
     assert L.lh_destroy(None) == 1
     assert L.lh_batch_launch(None) == 1
+    cfg = (ctypes.c_int32 * 3)(64, 2, 2)
+    assert L.lh_set_kernel_config(None, ctypes.byref(cfg)) == 1
+    assert L.lh_kernel_config(None, ctypes.byref(cfg)) == 1
 
 
 def test_create_without_device_reports_no_device():

@@ -181,3 +181,53 @@ def test_batched_tuner_of_bf16_is_switched_off():
     with pytest.raises(lh.LhError) as e:
         bt.tune()
     assert e.value.status == 6
+
+
+# ---------------------------------------------------------------------------
+# Kernel configuration and the bfloat16 shadow's capacity.
+# ---------------------------------------------------------------------------
+def test_set_kernel_config_checks_the_shape():
+    lh = _lh()
+    g = rmat_graph(12, 3000, 30_000, seed=5)
+    tr = trainer_for(g, d=128, K=5, orders=2, dtype="bf16", seed=6, total_samples=1_000_000)
+    tr.set_kernel_config(32, 2, 4)
+    assert tr.kernel_config() == {"lanes_per_sample": 32, "units_per_lane": 2, "blocks_per_cu": 4}
+    for bad in ((16, 2, 4),   # 32 units < the 64 units of a bf16 row of 128
+                (8, 1, 4),    # not a compiled shape
+                (64, 1, 0), (64, 1, 65)):
+        with pytest.raises(lh.LhError) as e:
+            tr.set_kernel_config(*bad)
+        assert e.value.status == 1
+    assert tr.kernel_config() == {"lanes_per_sample": 32, "units_per_lane": 2, "blocks_per_cu": 4}
+    tr.train_steps(0, 100_000)
+    tr.check()
+    assert np.all(np.isfinite(tr.read(lh.LH_TABLE_U).cpu().numpy()))
+
+
+def test_bf16_shadow_capacity_with_imported_tables():
+    """Imported alias tables carry no degrees, so every node asks for a shadow slot; with
+    more nodes than the shadow holds (n = 150,000 > 131,072 slots) the first 131,072 get
+    one and the rest take the table path.  Training must stay sound: finite tables and
+    held-out AUC close to the same run on tables built (with degrees) on the device."""
+    lh = _lh()
+    g0 = rmat_graph(18, 150_000, 1_500_000, seed=41)
+    from synth.graphs import auc_negatives, holdout_split
+    g, hs, hd = holdout_split(g0, seed=42)
+    neg = auc_negatives(g0.n, g0.src, g0.dst, hs, seed=43)
+    T = 10 * g.m
+    built = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T)
+    imp = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T, build=False)
+    for which in (lh.LH_ALIAS_EDGE, lh.LH_ALIAS_NEG):
+        thr, al = built.export_alias(which)
+        imp.import_alias(which, thr, al)
+    imp.check()
+    results = []
+    for tr in (built, imp):
+        tr.train_steps(0, T)
+        tr.check()
+        for t in (lh.LH_TABLE_U, lh.LH_TABLE_C):
+            assert np.all(np.isfinite(tr.read(t).cpu().numpy()))
+        results.append(_auc_uc_uu(tr, hs, hd, neg))
+    print(f"n={g.n}: built uc {results[0][0]:.4f} uu {results[0][1]:.4f}; imported uc {results[1][0]:.4f} "
+          f"uu {results[1][1]:.4f}", flush=True)
+    assert abs(results[0][0] - results[1][0]) <= 0.01 and abs(results[0][1] - results[1][1]) <= 0.01
