@@ -121,7 +121,7 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     GraphDev g = graph_dev(h);
     g.eta_scale = 0.0f;  // dry run: every row is written back unchanged
     const int lps_opts[] = {2, 4, 8, 16, 32, 64};
-    const int bpc_opts[] = {2, 4, 8, 16};
+    const int bpc_opts[] = {1, 2, 3, 4, 8, 16};
     TileCfg best = h->cfg;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
