@@ -80,12 +80,11 @@ typedef struct {
     int64_t batch;      /* SNAPSHOT batch B (samples [bB, (b+1)B) share one snapshot)      */
     double hot_rate;    /* HOGWILD: a row r is "hot" when W p_r >= hot_rate, p_r = the
                            probability that one sample touches r (from the degrees of the
-                           last lh_build_alias), W = samples in flight + samples for which
-                           a row stays cached in one XCD's L2 (unbounded when the tables
-                           fit in one L2: every touched row is hot).  Hot rows take
-                           coherent atomic increments, the others plain stores.  Rows of
-                           imported alias tables are hot.  <= 0: every row atomic;
-                           >= 1e30: none.                                                */
+                           last lh_build_alias), W = the launch's samples in flight
+                           (unbounded when the tables fit in one XCD's L2: every touched
+                           row is hot).  Hot rows take atomic increments, the others
+                           coherent (system-scope) stores.  Rows of imported alias
+                           tables are hot.  <= 0: every row atomic; >= 1e30: none.       */
     double max_conflicts; /* HOGWILD: the launch keeps F samples in flight with
                            F (2 + K) / n_active <= max_conflicts, n_active = nodes with an
                            arc, so that a row of average traffic has at most this many

@@ -45,12 +45,8 @@ GraphDev graph_dev(const lh_handle *h)
         g.max_in_flight = h->p.max_conflicts * (double)h->n_active / (double)(h->p.K + 2);
     const double b = h->p.dtype == LH_FP32 ? 4.0 : 2.0;
     const double ntab = h->p.orders == LH_ORDER12 ? 3.0 : (h->p.orders == LH_ORDER2 ? 2.0 : 1.0);
-    const double nord = h->p.orders == LH_ORDER12 ? 2.0 : 1.0;
     const double rows = (double)(h->n_active > 0 ? h->n_active : h->n);
-    // The residency window is a lower bound, so it counts the most bytes a sample can bring
-    // into L2: bfloat16 Hogwild rows in the binary32 shadow move as 4-byte values.
-    const double b_res = uses_shadow(h->p.dtype, h->p.mode) ? 4.0 : b;
-    g.resid = l2_residency(h->l2_bytes, rows * h->p.d * b * ntab, nord * (h->p.K + 2) * h->p.d * b_res);
+    g.resid = small_table_window(h->l2_bytes, rows * h->p.d * b * ntab);
     ShadowCtx sc;
     const bool shadowed = shadow_ctx(h, &sc);
     for (int t = 0; t < 3; ++t) g.shadow[t] = shadowed ? sc.shadow[t] : nullptr;

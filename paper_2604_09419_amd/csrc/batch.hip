@@ -300,10 +300,8 @@ static int batch_occupancy(const lh_batch *b, int variant, int *ls_out)
 // The schedule of a batched launch, its grid and each graph's heat threshold.  Graph g
 // holds the share phi_g = T_g / sum T of the samples in flight (the schedule interleaves
 // the graphs in proportion), so the grid is lowered until phi_g F stays within every
-// graph's staleness cap.  The L2 residency window of each graph is the one it has when
-// trained alone: other graphs' lines can only evict its lines sooner, so this errs
-// towards more hot rows (a lower bound from the graphs' summed footprint was measured
-// to leave rows of small graphs stale).
+// graph's staleness cap.  A graph whose tables fit in one L2 has all rows hot, as when
+// it is trained alone.
 static void batch_items(lh_batch *b, unsigned long long item_samples, bool dry, unsigned long long probe)
 {
     unsigned long long acc = 0, total = 0;

@@ -26,7 +26,7 @@ struct GraphDev {
     int hot_heat;              // rows with heat <= hot_heat take atomic increments (-1: none)
     double hot_rate;           // host side: the threshold hot_heat is derived from per launch
     double max_in_flight;      // host side: cap on samples in flight (0: none)
-    double resid;              // host side: samples a row stays cached in one XCD's L2 (inf: whole launch)
+    double resid;              // host side: extra hot window (infinite for tables that fit in one L2)
     // bfloat16 Hogwild: binary32 shadow rows of the hot rows ([cap x d] per table) and the
     // per-node slot map (slot >= 0: the row lives in the shadow for this launch).  NULL
     // for binary32 tables and SNAPSHOT.
@@ -84,19 +84,14 @@ struct ShadowCtx {
     unsigned long long seed, sr_key;
 };
 
-// XCDs of one MI355X; each has its own L2, and the L2s are not kept coherent with each
-// other for ordinary loads and stores within a kernel.
-constexpr int kXcds = 8;
-
-// Samples (chip-wide) for which a row line, once in one XCD's L2, stays there: each XCD
-// sees one sample in kXcds and each sample brings at most bytes_per_sample of new lines,
-// so a line survives at least kXcds * l2_bytes / bytes_per_sample samples.  Tables whose
-// footprint fits in one L2 stay cached for the whole launch (infinity).
-inline double l2_residency(double l2_bytes, double footprint, double bytes_per_sample)
+// Extra window added to the samples in flight when choosing hot rows: unbounded (every
+// row hot) when the tables fit in one XCD's L2, where atomics stay on chip and the few rows
+// collide constantly; else none (rows are read and written coherently, see tile.hpp).
+inline double small_table_window(double l2_bytes, double footprint)
 {
-    if (footprint <= l2_bytes) return __builtin_inf();
-    return bytes_per_sample > 0.0 ? (double)kXcds * l2_bytes / bytes_per_sample : 0.0;
+    return footprint <= l2_bytes ? __builtin_inf() : 0.0;
 }
+
 ScratchLayout scratch_layout(long long n, long long m);
 
 constexpr int RADIX_ITEMS = 16;

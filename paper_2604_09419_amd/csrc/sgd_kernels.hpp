@@ -50,11 +50,10 @@ inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_pe
     return (unsigned)blocks;
 }
 
-// Heat threshold for a launch whose rows stay exposed for a window of W samples (those in
-// flight plus those for which a row stays cached in one XCD's L2; infinite when the tables
-// fit in one L2): a row is hot when W p_r reaches hot_rate, i.e. when
-// floor(-log2 p_r) <= floor(log2(W / hot_rate)).  hot_rate <= 0 makes every row hot,
-// hot_rate >= 1e30 none.
+// Heat threshold for a launch whose rows are exposed to a window of W samples (those in
+// flight, or unbounded for tables that fit in one L2): a row is hot when W p_r reaches
+// hot_rate, i.e. when floor(-log2 p_r) <= floor(log2(W / hot_rate)).  hot_rate <= 0 makes
+// every row hot, hot_rate >= 1e30 none.
 inline int hot_heat_for(double W, double hot_rate)
 {
     if (!(hot_rate > 0.0)) return 255;

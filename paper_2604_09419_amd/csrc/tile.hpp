@@ -114,6 +114,21 @@ struct Rows {
     uint32_t b[KMAX + 1][UPL];
 };
 
+// Table rows are read and (when cold) written with system-scope accesses (sc0 sc1 on
+// gfx950).  The eight XCDs' L2 caches are not kept coherent with each other for ordinary
+// accesses: a row written by one XCD would stay dirty in that L2 while the others read
+// the old copy from memory.  System scope makes the accesses coherent across XCDs, at
+// about 1 % of the training kernel's speed (measured on the C2 workload).
+__device__ __forceinline__ uint32_t load_coherent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void store_coherent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <typename TT, int LPS, int UPL>
 __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint32_t (&o)[UPL])
 {
@@ -122,49 +137,71 @@ __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint
     for (int k = 0; k < UPL; ++k) {
         const int un = k * LPS + gl;
         uint32_t v = 0u;
-        if (un < nunits) v = w[un];
+        if (un < nunits) v = load_coherent(w + un);
         o[k] = v;
     }
 }
 
-// Row `id` of table t: the table row, or (bfloat16, id < 0) shadow row ~id, whose binary32
-// values are rounded to nearest even for the arithmetic.  A shadow row holds the even
-// elements of the row and then the odd ones (element 2 un + e at e * d / 2 + un), so the
-// lanes of a group touch contiguous words for each half.
+// Raw words of row `id` of table t for this lane.  binary32: the row's units.  bfloat16:
+// lo = the table row's units (two values each), or (id < 0) the even half of shadow row
+// ~id as binary32 bits, with hi = its odd half (a shadow row holds the even elements of
+// the row and then the odd ones, element 2 un + e at e * d / 2 + un, so the lanes of a
+// group touch contiguous words for each half).  The address is chosen without a branch
+// and nothing here uses the loaded words, so every row's loads of a sample are in flight
+// together; shadow rows are packed afterwards by pack_shadow_row.
 template <typename TT, int LPS, int UPL>
-__device__ __forceinline__ void load_row_of(const GraphDev &g, int t, int id, int gl, uint32_t (&o)[UPL])
+__device__ __forceinline__ void load_row_raw(const GraphDev &g, int t, int id, int gl, uint32_t (&lo)[UPL],
+                                             uint32_t (&hi)[UPL])
 {
-    if constexpr (sizeof(TT) == 2) {
-        if (id < 0) {
-            const float *sw = g.shadow[t] + (long long)(~id) * g.d;
-            const int half = g.nunits;
+    const int nu = g.nunits;
+    if constexpr (sizeof(TT) == 4) {
+        load_row<TT, LPS, UPL>((const TT *)g.tab[t] + (long long)id * g.d, nu, gl, lo);
+    } else {
+        const bool sh = id < 0;
+        const uint32_t *tw = reinterpret_cast<const uint32_t *>((const TT *)g.tab[t] + (long long)(sh ? 0 : id) * g.d);
+        const uint32_t *sw = reinterpret_cast<const uint32_t *>(g.shadow[t] + (long long)(sh ? ~id : 0) * g.d);
+        const uint32_t *pa = sh ? sw : tw;
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) {
-                const int un = k * LPS + gl;
-                uint32_t v = 0u;
-                if (un < half) v = f32_to_bf16_rne(sw[un]) | (f32_to_bf16_rne(sw[half + un]) << 16);
-                o[k] = v;
-            }
-            return;
+        for (int k = 0; k < UPL; ++k) {
+            const int un = k * LPS + gl;
+            lo[k] = un < nu ? load_coherent(pa + un) : 0u;
+            hi[k] = (sh && un < nu) ? load_coherent(sw + nu + un) : 0u;
         }
     }
-    load_row<TT, LPS, UPL>((const TT *)g.tab[t] + (long long)id * g.d, g.nunits, gl, o);
+}
+
+// bfloat16: a shadow row's words become units rounded to nearest even (no-op otherwise).
+template <typename TT, int UPL>
+__device__ __forceinline__ void pack_shadow_row(int id, uint32_t (&lo)[UPL], const uint32_t (&hi)[UPL])
+{
+    if constexpr (sizeof(TT) == 2) {
+#pragma unroll
+        for (int k = 0; k < UPL; ++k) {
+            const uint32_t p = f32_to_bf16_rne(__uint_as_float(lo[k])) | (f32_to_bf16_rne(__uint_as_float(hi[k])) << 16);
+            lo[k] = id < 0 ? p : lo[k];
+        }
+    }
 }
 
 template <typename TT, int LPS, int UPL, int KMAX>
 __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, int tA, int tB, int u,
                                           const int (&ids)[KMAX + 1], int K, int gl)
 {
-    load_row_of<TT, LPS, UPL>(g, tA, u, gl, r.a);
+    uint32_t ah[UPL], bh[KMAX + 1][UPL];
+    load_row_raw<TT, LPS, UPL>(g, tA, u, gl, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j <= K) {
-            load_row_of<TT, LPS, UPL>(g, tB, ids[j], gl, r.b[j]);
+            load_row_raw<TT, LPS, UPL>(g, tB, ids[j], gl, r.b[j], bh[j]);
         } else {
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) r.b[j][k] = 0u;
+            for (int k = 0; k < UPL; ++k) r.b[j][k] = bh[j][k] = 0u;
         }
     }
+    pack_shadow_row<TT, UPL>(u, r.a, ah);
+#pragma unroll
+    for (int j = 0; j <= KMAX; ++j)
+        if (j <= K) pack_shadow_row<TT, UPL>(ids[j], r.b[j], bh[j]);
 }
 
 // Write one row back: new = old + inc.  `hot` asks for the atomic path.
@@ -223,7 +260,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
                 for (int e = 0; e < EPU; ++e) x[e] = val<TT>(old[k], e) + inc[k][e];
                 uint32_t rnd = 0u;
                 if constexpr (EPU == 2) rnd = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
-                w[un] = f32_to_unit<TT>(x, rnd);
+                store_coherent(w + un, f32_to_unit<TT>(x, rnd));
             }
         }
     } else {

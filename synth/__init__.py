@@ -14,5 +14,6 @@ from .graphs import (  # noqa: F401
     batch_graph_specs,
     batch_graph,
     small_batch,
+    mid_graph,
     CONFIGS,
 )

@@ -273,3 +273,15 @@ def small_batch(G: int = 6):
         out.append(dict(graph=tr, held_src=hs, held_dst=hd, neg_dst=neg, T=20 * tr.m,
                         d=64 if gi % 2 == 0 else 128, seed=10 + gi, graph_id=gi))
     return out
+
+
+def mid_graph():
+    """A mid-size workload whose tables are a few times the GPU's total L2 (where rows written
+    by one XCD are most often read by another): directed R-MAT scale 18 restricted to
+    150,000 nodes, 1,500,000 unique arcs (seed 41), unit weights, a 1 % held-out split
+    (seed 42) with evaluation negatives (seed 43); d = 64, K = 5, second order, 10 epochs
+    (T = 10 m), training seed 7.  Returns a dict like small_batch's entries."""
+    g = rmat_graph(18, 150_000, 1_500_000, seed=41)
+    tr, hs, hd = holdout_split(g, seed=42)
+    neg = auc_negatives(g.n, g.src, g.dst, hs, seed=43)
+    return dict(graph=tr, held_src=hs, held_dst=hd, neg_dst=neg, T=10 * tr.m, d=64, seed=7, graph_id=0)

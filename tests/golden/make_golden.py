@@ -3,6 +3,7 @@
     python tests/golden/make_golden.py c1_auc    # seconds
     python tests/golden/make_golden.py c2_auc    # about 35 minutes, single thread
     python tests/golden/make_golden.py batch6_auc  # about a minute
+    python tests/golden/make_golden.py mid_auc     # about a minute
 
 Each output JSON records the command, the workload and the oracle's binary64 result.
 """
@@ -17,7 +18,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
-from synth import CONFIGS, config_graph, small_batch  # noqa: E402
+from synth import CONFIGS, config_graph, mid_graph, small_batch  # noqa: E402
 
 
 def run_auc(name: str, orders: int, T: int, d: int, out: str):
@@ -76,6 +77,25 @@ def run_batch6(out: str):
         json.dump(res, f, indent=1)
 
 
+def run_mid(out: str):
+    """Second-order held-out AUCs (uc, uu) of the mid-size workload, SEQ mode."""
+    t0 = time.time()
+    it = mid_graph()
+    g, hs, hd, neg = it["graph"], it["held_src"], it["held_dst"], it["neg_dst"]
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+    m = oracle.Model(tb, d=it["d"], K=5, orders=2, T=it["T"], seed=it["seed"], graph_id=it["graph_id"])
+    m.train(0, it["T"], "seq")
+    res = {"workload": "synth.mid_graph", "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": it["d"],
+           "K": 5, "orders": 2, "T": it["T"], "seed": it["seed"], "mode": "seq", "precision": "binary64",
+           "auc_uc": oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2)),
+           "auc_uu": oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg)),
+           "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    res["oracle_seconds"] = round(time.time() - t0, 1)
+    with open(os.path.join(HERE, out), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 if __name__ == "__main__":
     which = sys.argv[1]
     if which == "c1_auc":
@@ -84,5 +104,7 @@ if __name__ == "__main__":
         run_auc("C2", orders=3, T=CONFIGS["C2"]["T"], d=CONFIGS["C2"]["d"], out="c2_oracle_auc.json")
     elif which == "batch6_auc":
         run_batch6("batch6_oracle_auc.json")
+    elif which == "mid_auc":
+        run_mid("mid_oracle_auc.json")
     else:
         raise SystemExit(__doc__)

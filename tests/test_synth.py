@@ -59,3 +59,13 @@ def test_small_batch_matches_stored_oracle_aucs():
     for it, ref in zip(small_batch(6), gold["graphs"]):
         assert (it["graph"].n, it["graph"].m, it["held_src"].size, it["d"], it["T"], it["seed"]) == \
             (ref["n"], ref["m_train"], ref["held_out"], ref["d"], ref["T"], ref["seed"])
+
+
+def test_mid_graph_matches_stored_oracle_aucs():
+    import json
+    import os
+    from synth import mid_graph
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mid_oracle_auc.json")))
+    it = mid_graph()
+    assert (it["graph"].n, it["graph"].m, it["held_src"].size, it["T"], it["seed"]) == \
+        (gold["n"], gold["m_train"], gold["held_out"], gold["T"], gold["seed"])
