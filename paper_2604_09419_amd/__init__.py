@@ -41,7 +41,7 @@ class Trainer:
     def __init__(self, n: int, src, dst, w, d: int, K: int = 5, orders: int = 2, dtype: str = "fp32",
                  eta0: float = 0.025, lam: float = 0.0, alpha_neg: float = 1.0, seed: int = 1,
                  total_samples: int = 1, mode: str = "hogwild", batch: int = 0, graph_id: int = 0,
-                 hot_rate: float = 1.0, max_conflicts: float = 0.5,
+                 hot_rate: float = 0.75, max_conflicts: float = 0.25,
                  device: int = 0, stream=None, build: bool = True, init: bool = True):
         torch = _torch()
         self.torch = torch

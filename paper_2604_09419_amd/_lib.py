@@ -121,7 +121,7 @@ def check(status: int, where: str, handle=None) -> None:
 def make_params(d: int, K: int = 5, orders: int = LH_ORDER2, dtype: int = LH_FP32, eta0: float = 0.025,
                 lam: float = 0.0, alpha_neg: float = 1.0, seed: int = 1, total_samples: int = 1,
                 mode: int = LH_HOGWILD, graph_id: int = 0, batch: int = 0,
-                hot_rate: float = 1.0, max_conflicts: float = 0.5) -> lh_params:
+                hot_rate: float = 0.75, max_conflicts: float = 0.25) -> lh_params:
     return lh_params(d, K, orders, dtype, eta0, lam, alpha_neg, seed, total_samples, mode, graph_id, batch,
                      hot_rate, max_conflicts)
 
