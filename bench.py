@@ -58,15 +58,27 @@ KERNEL_SOURCES = [
 ]
 
 
+def _code_only(text: str, python: bool) -> str:
+    """Source text without comments and with whitespace collapsed, so that the hash below
+    changes with the code, not with its comments (string literals are kept verbatim)."""
+    import re
+    if python:
+        pat = re.compile(r'("(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\')|#[^\n]*')
+    else:
+        pat = re.compile(r'("(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\')|//[^\n]*|/\*.*?\*/', re.S)
+    text = pat.sub(lambda m: m.group(1) or " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sources_sha256(root: str = ROOT) -> str:
-    """SHA-256 over KERNEL_SOURCES (path, NUL, contents, NUL each)."""
+    """SHA-256 over KERNEL_SOURCES (path, NUL, code without comments, NUL each)."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         h.update(rel.encode())
         h.update(b"\0")
-        with open(os.path.join(root, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, rel), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read(), rel.endswith(".py")).encode())
         h.update(b"\0")
     return h.hexdigest()
 

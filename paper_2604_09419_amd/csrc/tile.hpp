@@ -15,14 +15,15 @@
 //            per-row contributions (SNAPSHOT, Eq. (4)).
 //
 // HOGWILD write-back: a cold row is stored (row as loaded plus the sample's increment;
-// no locks).  A hot row -- one that many in-flight samples touch at once, a hub -- is
-// updated with atomic increments (binary32 float atomics; bfloat16: compare-and-swap
-// of the stochastically rounded sum, bounded retries), so concurrent updates of hubs
-// are not lost.  Atomics and device-wide visibility also keep the per-XCD L2 caches
-// from holding diverging copies of the hot rows.
+// no locks) with a system-scope store, and every table row is loaded with system scope,
+// so the eight XCDs' L2 caches never hold diverging copies.  A hot row -- one that an
+// in-flight sample is likely to share, a hub -- is updated with binary32 atomic
+// increments so that concurrent updates are not lost (bfloat16 tables keep their hot
+// rows in a binary32 shadow for the launch).
 //
 // All 1 + K dot products of a sample use the rows as loaded before the sample; a row
-// that appears in several slots of one sample receives the sum of its increments.
+// that appears in several slots of one sample receives the sum of its increments (each
+// occurrence is applied atomically).
 #pragma once
 
 #include "handle.hpp"

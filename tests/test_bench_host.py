@@ -47,3 +47,10 @@ def test_committed_traffic_summary_is_parseable():
         if sep:
             rec[k] = v
     assert float(rec["traffic_bytes_per_launch"]) > 0 and len(rec["kernel_sources_sha256"]) == 64
+
+
+def test_traffic_hash_ignores_comments_only():
+    code = "int a = 1; // note\n/* block\n comment */ const char *s = \\"// kept\\";\n"
+    assert bench._code_only(code, False) == bench._code_only(code.replace("note", "other"), False)
+    assert bench._code_only(code, False) != bench._code_only(code.replace("a = 1", "a = 2"), False)
+    assert "// kept" in bench._code_only(code, False)
