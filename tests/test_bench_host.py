@@ -50,7 +50,7 @@ def test_committed_traffic_summary_is_parseable():
 
 
 def test_traffic_hash_ignores_comments_only():
-    code = "int a = 1; // note\n/* block\n comment */ const char *s = \\"// kept\\";\n"
+    code = 'int a = 1; // note\n/* block\n comment */ const char *s = "// kept";\n'
     assert bench._code_only(code, False) == bench._code_only(code.replace("note", "other"), False)
     assert bench._code_only(code, False) != bench._code_only(code.replace("a = 1", "a = 2"), False)
     assert "// kept" in bench._code_only(code, False)
