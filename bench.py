@@ -265,16 +265,22 @@ def bench_batched(args):
 
 
 def bench_large(args):
-    """C5: directed R-MAT scale 26 (2^26 nodes, 2^30 arcs), bfloat16, second order, 1e10 samples."""
+    """C5: directed R-MAT scale 26 (2^26 nodes, 2^30 arcs), bfloat16, second order, 1e10
+    samples.  C5U: the uniform-endpoint control at the same shape (no hub rows, so every row
+    is cold: the kernel's raw random gather/scatter rate)."""
     import torch
     from paper_2604_09419_amd import Trainer
-    from synth.graphs import rmat_graph_gpu
+    from synth.graphs import rmat_graph_gpu, uniform_graph_gpu
     from synth import CONFIGS
-    cfg = CONFIGS["C5"]
+    name = args.workload
+    cfg = CONFIGS[name]
     t0 = time.time()
-    src, dst, w = rmat_graph_gpu(cfg["scale"], cfg["n"], cfg["m_unique"], cfg["seed"])
+    if name == "C5U":
+        src, dst, w = uniform_graph_gpu(cfg["n"], cfg["m_unique"], cfg["seed"])
+    else:
+        src, dst, w = rmat_graph_gpu(cfg["scale"], cfg["n"], cfg["m_unique"], cfg["seed"])
     torch.cuda.synchronize()
-    log(f"[bench] C5 graph generated on the GPU in {time.time() - t0:.1f}s")
+    log(f"[bench] {name} graph generated on the GPU in {time.time() - t0:.1f}s")
     T = int(cfg["T"]) if args.c5_samples is None else int(args.c5_samples)
     tr = Trainer(cfg["n"], src, dst, w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype="bf16",
                  seed=cfg["seed"], total_samples=T, build=False, init=False)
@@ -283,18 +289,19 @@ def bench_large(args):
     tr.build_alias()
     build_s = time.time() - tb
     tr.init_embeddings()
-    tr.init_embeddings()
     tr.train_steps(0, T)
     ms = tr.last_train_ms()
     tr.check()
     bps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 2)
     achieved = bps * T / (ms * 1e-3) / 1e9
+    graph = ("uniform random endpoints (control), unit weights" if name == "C5U"
+             else "directed R-MAT scale 26, lognormal weights")
     return {
-        "metric": "edge samples/sec at d=128,K=5 (C5, bf16)", "value": T / (ms * 1e-3),
+        "metric": f"edge samples/sec at d=128,K=5 ({name}, bf16)", "value": T / (ms * 1e-3),
         "unit": "edge samples/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "C5: directed R-MAT scale 26, 67108864 nodes, 2^30 arcs, lognormal weights, "
-                               "d=128, K=5, second order, bf16 tables", "T": T,
+        "config": {"workload": f"{name}: {graph}, 67108864 nodes, 2^30 arcs, d=128, K=5, second order, "
+                               "bf16 tables", "T": T,
                    "kernel_config": tr.kernel_config(), "alias_build_s": build_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_hogwild (bf16, order 2)",
@@ -307,8 +314,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5"])
-    ap.add_argument("--c5-samples", type=float, default=None, help="override T for C5")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5", "C5U"])
+    ap.add_argument("--c5-samples", type=float, default=None, help="override T for C5 and C5U")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
@@ -342,7 +349,7 @@ def main():
     if args.workload == "C4":
         print(json.dumps(bench_batched(args)), flush=True)
         return
-    if args.workload == "C5":
+    if args.workload in ("C5", "C5U"):
         print(json.dumps(bench_large(args)), flush=True)
         return
 
@@ -403,6 +410,7 @@ def main():
             "train_only_samples_per_s": T / (bms * 1e-3),
             "speedup_train_vs_fp32": ms_kern / bms,
             "speedup_step_vs_fp32": ms_step / (sum(bsteps) / len(bsteps)),
+            "kernel_config": tb.kernel_config(),
             "roofline": {"bound": "hbm", "achieved": bach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": bach / PEAK_HBM_GBS, "bytes_per_sample": bbps},
         }

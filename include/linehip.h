@@ -158,11 +158,15 @@ LH_API lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_path);
 
 /* The Hogwild kernel configuration in use: out[0] lanes per sample, out[1] 4-byte units
  * of a row per lane (one binary32 value or two bfloat16 values each), out[2] workgroups
- * per compute unit (host memory, 3 int32). */
+ * per compute unit (host memory, 3 int32).  Until lh_set_kernel_config or lh_tune pins
+ * one, lh_build_alias and lh_import_alias choose it from the degrees: bfloat16 handles
+ * run two samples per wavefront when at most a tenth of the row touches would then fall
+ * on hot rows, else one (imported tables, whose rows are all hot: one). */
 LH_API lh_status lh_kernel_config(const lh_handle *h, int32_t out[3]);
 
 /* Use configuration cfg (same layout as lh_kernel_config's out) for later Hogwild
- * launches, e.g. one found by the caller's own timing.  (lanes, units) must be one of
+ * launches, e.g. one found by the caller's own timing, and keep it across later alias
+ * builds.  (lanes, units) must be one of
  * (16|32|64, 1 or 2), (2..64, 4), (4..64, 8) with lanes x units >= the row's units, and
  * 1 <= workgroups <= 64; else LH_ERR_INVALID_ARG and the configuration is unchanged. */
 LH_API lh_status lh_set_kernel_config(lh_handle *h, const int32_t cfg[3]);

@@ -375,6 +375,7 @@ lh_status build_alias(lh_handle *h, void *scratch, size_t bytes)
     // The scratch may be released by the caller once this work has run.
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "alias build");
+    if (!h->cfg_pinned) h->cfg = auto_cfg(h);
     return LH_OK;
 }
 
@@ -424,6 +425,7 @@ lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32
                            (uint8_t *)(h->ws + h->lay.nheat), h->n, (uint8_t)0);
     for (int v = 0; v < 256; ++v) h->heat_count[v] = 0;
     h->heat_count[0] = (unsigned long long)h->n;
+    if (!h->cfg_pinned) h->cfg = auto_cfg(h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "alias import");
     if (which == LH_ALIAS_EDGE)

@@ -330,6 +330,7 @@ lh_status lh_set_kernel_config(lh_handle *h, const int32_t cfg[3])
     if (!cfg_supported(h->p.dtype, h->p.d, c))
         return fail(h, LH_ERR_INVALID_ARG, "no kernel for this (lanes, units, workgroups) at this width");
     h->cfg = c;
+    h->cfg_pinned = true;
     return LH_OK;
 }
 

@@ -114,6 +114,7 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
         c.blocks_per_cu = hit[2];
         if (cfg_supported(h->p.dtype, h->p.d, c)) {
             h->cfg = c;
+            h->cfg_pinned = true;
             return LH_OK;
         }
     }
@@ -155,6 +156,7 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->cfg = best;
+    h->cfg_pinned = true;
     int v[4] = {best.lps, best.upl, best.blocks_per_cu, 0};
     cache_store(cache_path, key, v);
     hipError_t e = hipGetLastError();

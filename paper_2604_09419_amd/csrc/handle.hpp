@@ -122,6 +122,7 @@ struct lh_handle {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     lh::TileCfg cfg;  // chosen Hogwild kernel configuration
+    bool cfg_pinned = false;  // set by lh_set_kernel_config or lh_tune: auto_cfg leaves it
     std::string err;
 };
 
@@ -141,6 +142,22 @@ void launch_sample(lh_handle *h, unsigned long long first, unsigned long long co
 void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *buf, bool write);
 TileCfg default_cfg(int dtype, int d);
 TileCfg natural_cfg(int dtype, int d);
+// Share of row touches (0..1) that fall on rows of heat <= hot_heat, from the per-heat node
+// counts: a node of heat v is touched by one sample with probability in [2^-(v+1), 2^-v)
+// (2^-(v+1/2) is taken) and a sample touches 2 + K rows of each table.
+double hot_touch_share(const unsigned long long *heat_count, int hot_heat, int K);
+// Samples in flight of a Hogwild launch of `count` samples in configuration c.
+double hogwild_in_flight(const GraphDev &g, int dtype, int orders, const TileCfg &c, unsigned long long count,
+                         int num_cu);
+// Largest hot share at which a bfloat16 handle runs two samples per wavefront.
+constexpr double kTwoPerWaveMaxHotShare = 0.1;
+// The Hogwild configuration of a handle none was pinned for, once its degrees are known.
+// bfloat16: two samples per wavefront (half the lanes, twice the units per lane) when at
+// most kTwoPerWaveMaxHotShare of the row touches then fall on hot rows, else one.  Two per
+// wavefront double the samples in flight, which hides more of the latency of random rows
+// in large tables, but they also enlarge the hot set, whose atomics cost more than that
+// gain where hub rows take a large share of the touches.  Binary32: default_cfg.
+TileCfg auto_cfg(const lh_handle *h);
 bool cfg_supported(int dtype, int d, const TileCfg &c);
 hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCfg &c,
                           unsigned long long first, unsigned long long end, int num_cu,

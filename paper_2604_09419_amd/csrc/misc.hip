@@ -108,10 +108,10 @@ TileCfg natural_cfg(int dtype, int d)
     return c;
 }
 
-// The Hogwild configuration before any tuning.  Binary32: the natural one.  bfloat16
-// (whose timing runs are switched off): one unit per lane over up to 64 lanes, the
-// widest atomic and store instructions per row, which measured fastest at d = 128
-// (319 M samples/s against 211 for four units per lane).
+// The Hogwild configuration before any tuning or degrees.  Binary32: the natural one.
+// bfloat16 (whose timing runs are switched off): one sample per wavefront, one 4-byte unit
+// per lane over up to 64 lanes (wider rows: more units per lane).  auto_cfg may move a
+// bfloat16 handle to two samples per wavefront once the degrees are known.
 TileCfg default_cfg(int dtype, int d)
 {
     if (dtype == LH_FP32) return natural_cfg(dtype, d);
@@ -127,6 +127,44 @@ TileCfg default_cfg(int dtype, int d)
         c.upl = next_pow2(LH_CDIV(nu, 64));
     }
     return c;
+}
+
+double hot_touch_share(const unsigned long long *heat_count, int hot_heat, int K)
+{
+    if (hot_heat < 0) return 0.0;
+    if (hot_heat >= 255) return 1.0;
+    double touches = 0.0;
+    for (int v = 0; v <= hot_heat; ++v) touches += (double)heat_count[v] * std::exp2(-(v + 0.5));
+    const double share = touches / (2.0 + K);
+    return share < 1.0 ? share : 1.0;
+}
+
+double hogwild_in_flight(const GraphDev &g, int dtype, int orders, const TileCfg &c, unsigned long long count,
+                         int num_cu)
+{
+    if (dtype == LH_FP32) {
+        if (orders == 1) return hogwild_in_flight_t<float, 1>(g, c, count, num_cu);
+        if (orders == 2) return hogwild_in_flight_t<float, 2>(g, c, count, num_cu);
+        return hogwild_in_flight_t<float, 3>(g, c, count, num_cu);
+    }
+    if (orders == 1) return hogwild_in_flight_t<uint16_t, 1>(g, c, count, num_cu);
+    if (orders == 2) return hogwild_in_flight_t<uint16_t, 2>(g, c, count, num_cu);
+    return hogwild_in_flight_t<uint16_t, 3>(g, c, count, num_cu);
+}
+
+TileCfg auto_cfg(const lh_handle *h)
+{
+    TileCfg one = default_cfg(h->p.dtype, h->p.d);
+    if (h->p.dtype != LH_BF16 || h->p.mode != LH_HOGWILD) return one;
+    TileCfg two = one;
+    two.lps = one.lps / 2;
+    two.upl = one.upl * 2;
+    if (!cfg_supported(h->p.dtype, h->p.d, two)) return one;
+    const GraphDev g = graph_dev(h);
+    const double F = hogwild_in_flight(g, h->p.dtype, h->p.orders, two, h->p.total_samples, h->num_cu);
+    if (!(F > 0.0)) return one;
+    const int hot = hot_heat_for(F + g.resid, g.hot_rate);
+    return hot_touch_share(h->heat_count, hot, h->p.K) <= kTwoPerWaveMaxHotShare ? two : one;
 }
 
 bool cfg_supported(int dtype, int d, const TileCfg &c)

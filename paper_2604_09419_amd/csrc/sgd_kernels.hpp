@@ -105,21 +105,32 @@ inline double samples_in_flight(KernelT kernel, unsigned grid, int num_cu, int l
     X(64, 4)                \
     X(64, 8)
 
-// One Hogwild launch: the grid of the configuration, lowered if the graph's staleness
-// cap asks for fewer samples in flight, and the heat threshold for that concurrency.
-// With a shadow context (bfloat16 tables) the hot rows move into the binary32 shadow
-// for the launch and back afterwards; without one no row is read from a shadow.
+// The grid of one Hogwild launch over `count` samples and the samples it keeps in flight:
+// the configuration's grid, lowered if the graph's staleness cap asks for fewer.
 template <typename KernelT>
-hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c, unsigned long long first,
-                      unsigned long long end, int num_cu, const ShadowCtx *sc, hipStream_t s)
+inline double plan_launch(KernelT kern, int lps, const GraphDev &g, const TileCfg &c, unsigned long long count,
+                          int num_cu, unsigned *grid_out)
 {
-    unsigned grid = hogwild_grid(end - first, num_cu, c.blocks_per_cu);
+    unsigned grid = hogwild_grid(count, num_cu, c.blocks_per_cu);
     double F = samples_in_flight(kern, grid, num_cu, lps);
     if (g.max_in_flight > 0.0 && F > g.max_in_flight) {
         double per_block = 4.0 * (64.0 / lps);
         grid = (unsigned)std::max(1.0, std::floor(g.max_in_flight / per_block));
         F = samples_in_flight(kern, grid, num_cu, lps);
     }
+    *grid_out = grid;
+    return F;
+}
+
+// One Hogwild launch with the heat threshold for its concurrency.  With a shadow context
+// (bfloat16 tables) the hot rows move into the binary32 shadow for the launch and back
+// afterwards; without one no row is read from a shadow.
+template <typename KernelT>
+hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c, unsigned long long first,
+                      unsigned long long end, int num_cu, const ShadowCtx *sc, hipStream_t s)
+{
+    unsigned grid = 0;
+    const double F = plan_launch(kern, lps, g, c, end - first, num_cu, &grid);
     GraphDev gl = g;
     gl.hot_heat = hot_heat_for(F + g.resid, g.hot_rate);
     if (sc) {
@@ -132,6 +143,20 @@ hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && sc) e = shadow_end(*sc, gl.hot_heat, first, s);
     return e;
+}
+
+// Samples a Hogwild launch of `count` samples would keep in flight (0: no such kernel).
+template <typename TT, int ORD>
+double hogwild_in_flight_t(const GraphDev &g, const TileCfg &c, unsigned long long count, int num_cu)
+{
+    unsigned grid = 0;
+#define LH_PLAN_H(L, C)                                                                     \
+    if (c.lps == L && c.upl == C)                                                           \
+        return plan_launch(g.K <= 5 ? k_hogwild<TT, L, C, 5, ORD> : k_hogwild<TT, L, C, 8, ORD>, L, g, c, count, \
+                           num_cu, &grid);
+    LH_CFG_LIST(LH_PLAN_H)
+#undef LH_PLAN_H
+    return 0.0;
 }
 
 template <typename TT, int ORD>
@@ -174,12 +199,14 @@ hipError_t launch_snap_t(const GraphDev &g, const TileCfg &c, unsigned long long
     extern template hipError_t launch_hogwild_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long, \
                                                          unsigned long long, int, const ShadowCtx *, hipStream_t); \
     extern template hipError_t launch_snap_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long,    \
-                                                      unsigned long long, int, const SnapOut &, hipStream_t);
+                                                      unsigned long long, int, const SnapOut &, hipStream_t); \
+    extern template double hogwild_in_flight_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long, int);
 
 #define LH_DEFINE_LAUNCHERS(TT, ORD)                                                                    \
     template hipError_t launch_hogwild_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long, \
                                                   unsigned long long, int, const ShadowCtx *, hipStream_t); \
     template hipError_t launch_snap_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long,    \
-                                               unsigned long long, int, const SnapOut &, hipStream_t);
+                                               unsigned long long, int, const SnapOut &, hipStream_t); \
+    template double hogwild_in_flight_t<TT, ORD>(const GraphDev &, const TileCfg &, unsigned long long, int);
 
 }  // namespace lh

@@ -153,6 +153,9 @@ CONFIGS = {
                d=128, K=5, T=200_000_000, eta0=0.025, orders=3, dtype="bf16", holdout=True),
     "C5": dict(scale=26, n=1 << 26, m_unique=1 << 30, seed=5, directed=True, weights="lognormal",
                d=128, K=5, T=10_000_000_000, eta0=0.025, orders=2, dtype="bf16"),
+    # Uniform-endpoint control at C5's shape (raw random gather/scatter, no hub reuse).
+    "C5U": dict(n=1 << 26, m_unique=1 << 30, seed=55, directed=True, weights="unit",
+                d=128, K=5, T=10_000_000_000, eta0=0.025, orders=2, dtype="bf16"),
 }
 
 
@@ -246,6 +249,25 @@ def rmat_graph_gpu(scale: int, n: int, m_unique: int, seed: int, weights: str = 
         w = torch.ones(m_unique, dtype=torch.float32, device=device)
     else:
         w = torch.empty(m_unique, dtype=torch.float32, device=device).log_normal_(0.0, 1.0, generator=gen)
+    return src, dst, w
+
+
+def uniform_graph_gpu(n: int, m: int, seed: int, device: str = "cuda"):
+    """Control graph with uniformly random endpoints: m arcs, src uniform on [0, n), dst
+    uniform on [0, n) minus src (no self-loops; repeated arcs are kept, about m^2 / (2 n^2)
+    of them), unit weights.  Out-degrees are then binomial(m, 1/n), so the negative
+    distribution deg^0.75 is close to uniform too: rows are touched at near-equal rates and
+    no row is a hub.  Built on the GPU with torch's seeded generator; returns (src int32,
+    dst int32, w float32) on ``device``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    src = torch.randint(0, n, (m,), generator=gen, device=device, dtype=torch.int64)
+    off = torch.randint(1, n, (m,), generator=gen, device=device, dtype=torch.int64)
+    dst = ((src + off) % n).to(torch.int32)
+    del off
+    src = src.to(torch.int32)
+    w = torch.ones(m, dtype=torch.float32, device=device)
     return src, dst, w
 
 

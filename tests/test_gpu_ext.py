@@ -231,3 +231,29 @@ def test_bf16_shadow_capacity_with_imported_tables():
     print(f"n={g.n}: built uc {results[0][0]:.4f} uu {results[0][1]:.4f}; imported uc {results[1][0]:.4f} "
           f"uu {results[1][1]:.4f}", flush=True)
     assert abs(results[0][0] - results[1][0]) <= 0.01 and abs(results[0][1] - results[1][1]) <= 0.01
+
+
+def test_bf16_shape_follows_the_hot_share():
+    """Without a pinned shape, a bfloat16 handle runs two samples per wavefront when few
+    row touches fall on hot rows (uniform endpoints, 2^20 nodes: no row reaches the hot
+    rate) and one sample per wavefront where hub rows take most touches (the R-MAT mid
+    graph: about two thirds of the touches go to hot rows); a pinned shape survives a
+    rebuild of the alias tables."""
+    import torch
+    lh = _lh()
+    from synth.graphs import mid_graph, uniform_graph_gpu
+    src, dst, w = uniform_graph_gpu(1 << 20, 1 << 24, seed=9)
+    torch.cuda.synchronize()
+    uni = lh.Trainer(1 << 20, src, dst, w, d=128, K=5, orders=2, dtype="bf16", seed=9, total_samples=10_000_000)
+    assert uni.kernel_config() == {"lanes_per_sample": 32, "units_per_lane": 2, "blocks_per_cu": 16}
+    uni.train_steps(0, 10_000_000)
+    uni.check()
+    assert np.all(np.isfinite(uni.read(lh.LH_TABLE_C).cpu().numpy()))
+    uni.set_kernel_config(64, 1, 16)
+    uni.build_alias()
+    assert uni.kernel_config() == {"lanes_per_sample": 64, "units_per_lane": 1, "blocks_per_cu": 16}
+    uni.close()
+    del src, dst, w
+    g = mid_graph()["graph"]
+    hub = trainer_for(g, d=128, K=5, orders=2, dtype="bf16", seed=7, total_samples=10 * g.m)
+    assert hub.kernel_config() == {"lanes_per_sample": 64, "units_per_lane": 1, "blocks_per_cu": 16}
