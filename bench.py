@@ -120,13 +120,13 @@ def workload(name: str):
     return cfg, g, hs, hd, neg
 
 
-def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache):
+def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False):
     """Time `steps` full passes (after `warmup`); return timings and the trainer."""
     import torch
     from paper_2604_09419_amd import Trainer
     T = int(cfg["T"])
     tr = Trainer(g.n, g.src, g.dst, g.w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype=dtype,
-                 eta0=cfg["eta0"], seed=seed, total_samples=T, build=False, init=False)
+                 eta0=cfg["eta0"], seed=seed, total_samples=T, build=False, init=False, hot_shadow=hot_shadow)
     # Tuning happens once, outside the timed region, with the step size scaled to zero.
     tr.build_alias()
     if dtype == "fp32":  # bfloat16 timing runs are switched off in the library for now
@@ -223,7 +223,7 @@ def bench_batched(args):
     for sp in specs:
         src, dst, w = rmat_graph_gpu(sp["scale"], sp["n"], sp["m"], sp["seed"] + 100_000)
         tr = Trainer(sp["n"], src, dst, w, d=sp["d"], K=5, orders=2, dtype="bf16", seed=sp["seed"],
-                     graph_id=sp["g"], total_samples=sp["T"], stream=stream)
+                     graph_id=sp["g"], total_samples=sp["T"], stream=stream, hot_shadow=args.hot_shadow)
         trainers.append(tr)
     torch.cuda.synchronize()
     log(f"[bench] C4: 64 graphs generated and built in {time.time() - t0:.1f}s")
@@ -256,7 +256,8 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "C4: 64 directed R-MAT graphs, n log-uniform 1e3..2e6, mean degree 8..32, "
                                "lognormal weights, d in {64,128}, K=5, second order, bf16 tables, T_g = 20 m_g",
-                   "graphs": len(specs), "total_samples": total_T, "sum_m": sum(sp["m"] for sp in specs)},
+                   "graphs": len(specs), "total_samples": total_T, "sum_m": sum(sp["m"] for sp in specs),
+                   "hot_shadow": args.hot_shadow},
         "sequential_launches": {"ms": seq_ms, "samples_per_s": total_T / (seq_ms * 1e-3),
                                 "batched_speedup": seq_ms / ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -283,7 +284,7 @@ def bench_large(args):
     log(f"[bench] {name} graph generated on the GPU in {time.time() - t0:.1f}s")
     T = int(cfg["T"]) if args.c5_samples is None else int(args.c5_samples)
     tr = Trainer(cfg["n"], src, dst, w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype="bf16",
-                 seed=cfg["seed"], total_samples=T, build=False, init=False)
+                 seed=cfg["seed"], total_samples=T, build=False, init=False, hot_shadow=args.hot_shadow)
     del src, dst, w
     tb = time.time()
     tr.build_alias()
@@ -302,7 +303,7 @@ def bench_large(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{name}: {graph}, 67108864 nodes, 2^30 arcs, d=128, K=5, second order, "
                                "bf16 tables", "T": T,
-                   "kernel_config": tr.kernel_config(), "alias_build_s": build_s},
+                   "kernel_config": tr.kernel_config(), "alias_build_s": build_s, "hot_shadow": args.hot_shadow},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_hogwild (bf16, order 2)",
                      "bytes_per_sample": bps},
@@ -319,6 +320,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--hot-shadow", action="store_true",
+                    help="bfloat16 runs: hot rows accumulate in a binary32 shadow per launch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (HBM counter scale)")
@@ -401,7 +404,8 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_bf16:
-        tb, bsteps, bkern = run_gpu_leg(cfg, g, "bf16", max(1, args.steps), 1, seed, args.tune_cache)
+        tb, bsteps, bkern = run_gpu_leg(cfg, g, "bf16", max(1, args.steps), 1, seed, args.tune_cache,
+                                        hot_shadow=args.hot_shadow)
         bms = sum(bkern) / len(bkern)
         bbps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 2)
         bach = bbps * T / (bms * 1e-3) / 1e9
@@ -411,6 +415,7 @@ def main():
             "speedup_train_vs_fp32": ms_kern / bms,
             "speedup_step_vs_fp32": ms_step / (sum(bsteps) / len(bsteps)),
             "kernel_config": tb.kernel_config(),
+            "hot_shadow": args.hot_shadow,
             "roofline": {"bound": "hbm", "achieved": bach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": bach / PEAK_HBM_GBS, "bytes_per_sample": bbps},
         }

@@ -36,12 +36,14 @@ class Trainer:
     ``src``, ``dst`` (int32) and ``w`` (float32) may be numpy arrays or torch tensors.
     ``orders``: 1 (first), 2 (second) or 3 (both).  ``dtype``: "fp32" or "bf16".
     ``mode``: "hogwild" or "snapshot" (then ``batch`` samples per snapshot).
+    ``hot_shadow`` (bfloat16 Hogwild): hot rows accumulate in a binary32 shadow for each
+    launch instead of taking stochastically rounded packed bfloat16 atomics.
     """
 
     def __init__(self, n: int, src, dst, w, d: int, K: int = 5, orders: int = 2, dtype: str = "fp32",
                  eta0: float = 0.025, lam: float = 0.0, alpha_neg: float = 1.0, seed: int = 1,
                  total_samples: int = 1, mode: str = "hogwild", batch: int = 0, graph_id: int = 0,
-                 hot_rate: float = 0.75, max_conflicts: float = 0.25,
+                 hot_rate: float = 0.75, max_conflicts: float = 0.25, hot_shadow: bool = False,
                  device: int = 0, stream=None, build: bool = True, init: bool = True):
         torch = _torch()
         self.torch = torch
@@ -53,7 +55,8 @@ class Trainer:
         self.params = make_params(d=d, K=K, orders=orders, dtype=LH_FP32 if dtype == "fp32" else LH_BF16,
                                   eta0=eta0, lam=lam, alpha_neg=alpha_neg, seed=seed, total_samples=total_samples,
                                   mode=LH_HOGWILD if mode == "hogwild" else LH_SNAPSHOT, graph_id=graph_id,
-                                  batch=batch, hot_rate=hot_rate, max_conflicts=max_conflicts)
+                                  batch=batch, hot_rate=hot_rate, max_conflicts=max_conflicts,
+                                  hot_shadow=hot_shadow)
         self.h = _lib.lh_create(self.params, device)
         tdt = torch.float32 if dtype == "fp32" else torch.bfloat16
         # Inputs given as GPU tensors may still be in the making on the caller's stream.

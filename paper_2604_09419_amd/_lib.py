@@ -41,6 +41,7 @@ class lh_params(ctypes.Structure):
         ("batch", ctypes.c_int64),
         ("hot_rate", ctypes.c_double),
         ("max_conflicts", ctypes.c_double),
+        ("hot_shadow", ctypes.c_int32),
     ]
 
 
@@ -121,9 +122,9 @@ def check(status: int, where: str, handle=None) -> None:
 def make_params(d: int, K: int = 5, orders: int = LH_ORDER2, dtype: int = LH_FP32, eta0: float = 0.025,
                 lam: float = 0.0, alpha_neg: float = 1.0, seed: int = 1, total_samples: int = 1,
                 mode: int = LH_HOGWILD, graph_id: int = 0, batch: int = 0,
-                hot_rate: float = 0.75, max_conflicts: float = 0.25) -> lh_params:
+                hot_rate: float = 0.75, max_conflicts: float = 0.25, hot_shadow: bool = False) -> lh_params:
     return lh_params(d, K, orders, dtype, eta0, lam, alpha_neg, seed, total_samples, mode, graph_id, batch,
-                     hot_rate, max_conflicts)
+                     hot_rate, max_conflicts, int(bool(hot_shadow)))
 
 
 # ---- the C entry points, same names -----------------------------------------------------

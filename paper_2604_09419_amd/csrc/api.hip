@@ -65,6 +65,7 @@ static lh_status check_params(const lh_params *p)
     if (!std::isfinite(p->lambda) || p->lambda < 0) return LH_ERR_INVALID_ARG;
     if (!std::isfinite(p->alpha_neg)) return LH_ERR_INVALID_ARG;
     if (std::isnan(p->hot_rate) || std::isnan(p->max_conflicts)) return LH_ERR_INVALID_ARG;
+    if (p->hot_shadow != 0 && p->hot_shadow != 1) return LH_ERR_INVALID_ARG;
     if (p->total_samples == 0) return LH_ERR_INVALID_ARG;
     if (p->graph_id < 0) return LH_ERR_INVALID_ARG;
     if (p->mode != LH_HOGWILD && p->mode != LH_SNAPSHOT) return LH_ERR_INVALID_ARG;

@@ -57,9 +57,10 @@ struct ScratchLayout {
 
 WsLayout ws_layout(const lh_params &p, long long n, long long m);
 
-// bfloat16 Hogwild handles keep their hot rows in a binary32 shadow.  (Binary32 handles
-// apply their atomics to the table rows: a compact shadow measured no faster for them.)
-inline bool uses_shadow(int dtype, int mode) { return mode == LH_HOGWILD && dtype == LH_BF16; }
+// bfloat16 Hogwild handles that ask for it (hot_shadow = 1) keep their hot rows in a
+// binary32 shadow.  (Binary32 handles apply their atomics to the table rows: a compact
+// shadow measured no faster for them.)
+inline bool uses_shadow(const lh_params &p) { return p.mode == LH_HOGWILD && p.dtype == LH_BF16 && p.hot_shadow == 1; }
 
 // Shadow rows per table of a Hogwild handle with a shadow and n nodes: every node of a graph
 // of up to 2^17 nodes, else one node in 16.  The hot set of a launch is trimmed to fit.

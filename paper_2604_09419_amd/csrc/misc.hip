@@ -31,7 +31,7 @@ WsLayout ws_layout(const lh_params &p, long long n, long long m)
     L.erec = carve(off, sizeof(EdgeRec) * (size_t)(m > 0 ? m : 1));
     L.nrec = carve(off, sizeof(NegRec) * (size_t)(n > 0 ? n : 1));
     L.nheat = carve(off, (size_t)(n > 0 ? n : 1));
-    if (uses_shadow(p.dtype, p.mode)) {
+    if (uses_shadow(p)) {
         const size_t ntab = p.orders == LH_ORDER12 ? 3 : (p.orders == LH_ORDER2 ? 2 : 1);
         L.shadow_cap = shadow_capacity(n > 0 ? n : 1);
         L.slot = carve(off, 4 * (size_t)(n > 0 ? n : 1));
@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(256) k_shadow_store(ShadowDev a, long long bou
 
 bool shadow_ctx(const lh_handle *h, ShadowCtx *o)
 {
-    if (!uses_shadow(h->p.dtype, h->p.mode) || h->lay.shadow_cap <= 0 || !h->ws) return false;
+    if (!uses_shadow(h->p) || h->lay.shadow_cap <= 0 || !h->ws) return false;
     o->nheat = (const uint8_t *)(h->ws + h->lay.nheat);
     o->slot = (int32_t *)(h->ws + h->lay.slot);
     o->srows = (int32_t *)(h->ws + h->lay.srows);

@@ -11,10 +11,11 @@
 namespace lh {
 
 // Grid-stride over 64-sample tiles: wave w takes tiles w, w + W, w + 2W, ...  The register
-// budget is capped for at least 3 (binary32) or 4 (bfloat16) waves per SIMD: the
-// bfloat16 kernel is latency bound and measured fastest there, a few spills included.
+// budget is capped for at least 3 (binary32) or 5 (bfloat16) waves per SIMD.  The bfloat16
+// kernel is latency bound: 5 waves (96 registers, no spills) measured 2 % faster than 4
+// on both hub-heavy and large uniform tables, and 6 (with spills) slower.
 template <typename TT>
-constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 4 : 3; }
+constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 5 : 3; }
 
 template <typename TT, int LPS, int UPL, int KMAX, int ORD>
 __global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)

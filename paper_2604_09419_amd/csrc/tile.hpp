@@ -17,9 +17,11 @@
 // HOGWILD write-back: a cold row is stored (row as loaded plus the sample's increment;
 // no locks) with a system-scope store, and every table row is loaded with system scope,
 // so the eight XCDs' L2 caches never hold diverging copies.  A hot row -- one that an
-// in-flight sample is likely to share, a hub -- is updated with binary32 atomic
-// increments so that concurrent updates are not lost (bfloat16 tables keep their hot
-// rows in a binary32 shadow for the launch).
+// in-flight sample is likely to share, a hub -- is updated with atomic increments so that
+// concurrent updates are not lost: binary32 atomics for binary32 tables; for bfloat16
+// tables packed bfloat16 atomics of the increment rounded stochastically onto the row's
+// bfloat16 grid, or (on request) binary32 atomics into a binary32 shadow of the hot rows
+// that is rounded back into the table after the launch.
 //
 // All 1 + K dot products of a sample use the rows as loaded before the sample; a row
 // that appears in several slots of one sample receives the sum of its increments (each
@@ -207,10 +209,15 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
 
 // Write one row back: new = old + inc.  `hot` asks for the atomic path.
 //   binary32: stored, or atomic increments;
-//   bfloat16: table rows (id >= 0) are stored with stochastic rounding, the random bits
-//   of unit un being lowbias32(sr + (ctr * 256 + un) * phi), or (hot: a row repeated
-//   within the sample) get packed bfloat16 atomic adds; shadow rows (id < 0, even
-//   elements then odd ones) always get binary32 atomic increments.
+//   bfloat16 table rows (id >= 0): with the random bits of unit un being
+//   lowbias32(sr + (ctr * 256 + un) * phi), a cold row is stored as the stochastic
+//   rounding SR(old + inc); a hot row receives, by packed bfloat16 atomic adds, the
+//   increments SR(old + inc) - old, which are exact multiples of the row's bfloat16 spacing
+//   (units whose increments are both zero are skipped).  Where no other write changed the
+//   unit since it was loaded, the atomic result is exactly SR(old + inc), the value a cold
+//   store would have written; otherwise the increment lands on the changed value, and the
+//   atomic unit rounds the sum where it is not representable.  Shadow rows (id < 0, even
+//   elements then odd ones) get binary32 atomic increments.
 template <typename TT, int LPS, int UPL>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
@@ -234,17 +241,23 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
             return;
         }
         if (hot) {
-            // a table row repeated within the sample: packed bfloat16 atomic adds of the
-            // increments rounded to nearest even
             uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
                 const int un = k * LPS + gl;
                 if (un < nunits) {
-                    const uint32_t p = f32_to_bf16_rne(inc[k][0]) | (f32_to_bf16_rne(inc[k][1]) << 16);
-                    __builtin_amdgcn_global_atomic_fadd_v2bf16(
-                        (short2_t __attribute__((address_space(1))) *)(w + un),
-                        __builtin_bit_cast(short2_t, p));
+                    const uint32_t rnd = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
+                    uint32_t p = 0u;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float o = val<TT>(old[k], e);
+                        const float nv = __uint_as_float(f32_to_bf16_sr(o + inc[k][e], rnd >> (16 * e)) << 16);
+                        p |= f32_to_bf16_rne(nv - o) << (16 * e);
+                    }
+                    if ((p & 0x7fff7fffu) != 0u)
+                        __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                            (short2_t __attribute__((address_space(1))) *)(w + un),
+                            __builtin_bit_cast(short2_t, p));
                 }
             }
             return;
@@ -461,11 +474,12 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
                 for (int jj = 0; jj < j; ++jj)
                     if (my_ids[jj] == my_ids[j]) my_dup |= (1u << j) | (1u << jj);
             }
-            // bfloat16 Hogwild: the rows with a shadow slot are this launch's hot rows; their
-            // ids become ~slot (negative, so equal rows stay equal and never meet a table id).
+            // bfloat16 Hogwild with a shadow: the rows with a shadow slot are this launch's
+            // hot rows; their ids become ~slot (negative, so equal rows stay equal and never
+            // meet a table id).
             if constexpr (sizeof(TT) == 2 && !SNAP) {
-                my_hot = 0;
                 if (g.slot) {
+                    my_hot = 0;
                     int sl[KMAX + 2];
                     sl[0] = g.slot[my_u];
 #pragma unroll

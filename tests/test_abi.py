@@ -76,6 +76,21 @@ def test_workspace_sizes(L):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     for n, m in [(0, 10), (1 << 31, 10), (10, -1)]:
         assert L.lh_workspace_size(ctypes.byref(p), n, m, ctypes.byref(a), ctypes.byref(b)) == 1
+    # bfloat16 Hogwild: the binary32 shadow of the hot rows (max(2^17, n/16) rows of d
+    # values per table) is in the workspace only when asked for
+    bf = _params(dtype=1, d=128, orders=3)
+    plain, _ = _lib.lh_workspace_size(bf, 10_000, 200_000)
+    shadowed, _ = _lib.lh_workspace_size(_params(dtype=1, d=128, orders=3, hot_shadow=True), 10_000, 200_000)
+    assert shadowed >= plain + 3 * 10_000 * 128 * 4
+    assert _lib.lh_workspace_size(_params(hot_shadow=True), 10_000, 200_000)[0] == persist
+
+
+def test_hot_shadow_must_be_0_or_1(L):
+    p = _params(dtype=1)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    for v, want in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+        p.hot_shadow = v
+        assert L.lh_workspace_size(ctypes.byref(p), 100, 1000, ctypes.byref(a), ctypes.byref(b)) == want
 
 
 def test_null_handles_rejected(L):

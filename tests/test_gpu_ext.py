@@ -28,26 +28,30 @@ def _auc_uc_uu(tr, hs, hd, neg):
             oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg)))
 
 
-def test_bf16_hogwild_c1_auc_matches_oracle():
+@pytest.mark.parametrize("hot_shadow", [False, True])
+def test_bf16_hogwild_c1_auc_matches_oracle(hot_shadow):
+    """C1's tables fit in one L2, so every touched row is hot: this exercises the hot-row
+    write path alone (packed bfloat16 atomics, or the binary32 shadow)."""
     gold = json.load(open(os.path.join(GOLDEN, "c1_oracle_auc.json")))
     g, hs, hd, neg = config_graph("C1", holdout=True)
-    tr = trainer_for(g, d=16, K=5, orders=2, dtype="bf16", seed=gold["seed"], total_samples=gold["T"])
+    tr = trainer_for(g, d=16, K=5, orders=2, dtype="bf16", seed=gold["seed"], total_samples=gold["T"],
+                     hot_shadow=hot_shadow)
     tr.train_steps(0, gold["T"])
     tr.check()
     uc, uu = _auc_uc_uu(tr, hs, hd, neg)
-    print(f"C1 bf16 hogwild AUC uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} "
+    print(f"C1 bf16 hogwild{' shadow' if hot_shadow else ''} AUC uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} "
           f"(oracle {gold['auc_uu']:.4f})", flush=True)
     assert abs(uc - gold["auc_uc"]) <= 0.005 and abs(uu - gold["auc_uu"]) <= 0.005
 
 
 def test_bf16_zero_step_leaves_tables_bitwise():
     """With eta0 = 0 every written value is already bfloat16, and stochastic rounding of an
-    exactly representable value returns it unchanged."""
+    exactly representable value returns it unchanged (hot rows: a zero increment)."""
     lh = _lh()
     g = rmat_graph(12, 3000, 30_000, seed=3)
-    for mode in ("hogwild", "snapshot"):
+    for mode, shadow in (("hogwild", False), ("hogwild", True), ("snapshot", False)):
         tr = trainer_for(g, d=64, K=5, orders=3, dtype="bf16", eta0=0.0, seed=4, total_samples=100_000,
-                         mode=mode, batch=4096)
+                         mode=mode, batch=4096, hot_shadow=shadow)
         before = [tr.read(t).cpu().numpy() for t in (0, 1, 2)]
         tr.train_steps(0, 100_000 if mode == "hogwild" else 4096 * 10)
         tr.check()
@@ -205,7 +209,8 @@ def test_set_kernel_config_checks_the_shape():
 
 
 def test_bf16_shadow_capacity_with_imported_tables():
-    """Imported alias tables carry no degrees, so every node asks for a shadow slot; with
+    """(bfloat16 with the binary32 shadow of the hot rows.)  Imported alias tables carry no
+    degrees, so every node asks for a shadow slot; with
     more nodes than the shadow holds (n = 150,000 > 131,072 slots) the first 131,072 get
     one and the rest take the table path.  Training must stay sound: finite tables and
     held-out AUC close to the same run on tables built (with degrees) on the device."""
@@ -215,8 +220,8 @@ def test_bf16_shadow_capacity_with_imported_tables():
     g, hs, hd = holdout_split(g0, seed=42)
     neg = auc_negatives(g0.n, g0.src, g0.dst, hs, seed=43)
     T = 10 * g.m
-    built = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T)
-    imp = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T, build=False)
+    built = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T, hot_shadow=True)
+    imp = trainer_for(g, d=64, K=5, orders=2, dtype="bf16", seed=7, total_samples=T, build=False, hot_shadow=True)
     for which in (lh.LH_ALIAS_EDGE, lh.LH_ALIAS_NEG):
         thr, al = built.export_alias(which)
         imp.import_alias(which, thr, al)

@@ -357,24 +357,26 @@ def test_gpu_inputs_made_on_the_callers_stream_are_waited_for():
         assert np.array_equal(t1, t2) and np.array_equal(a1, a2)
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
-def test_hogwild_mid_graph_auc_matches_oracle(dtype):
+@pytest.mark.parametrize("dtype,hot_shadow", [("fp32", False), ("bf16", False), ("bf16", True)])
+def test_hogwild_mid_graph_auc_matches_oracle(dtype, hot_shadow):
     """A graph whose tables are a few times the GPU's total L2: rows written by one XCD are
     often read by another before leaving the writer's L2.  Held-out AUCs must match the
-    binary64 oracle within 0.005 (plain stores here were 0.016 off)."""
+    binary64 oracle within 0.005 (plain stores here were 0.016 off), for bfloat16 with both
+    write paths of the hot rows."""
     from synth import mid_graph
     lh = _lh()
     gold = json.load(open(os.path.join(GOLDEN, "mid_oracle_auc.json")))
     it = mid_graph()
     g, hs, hd, neg = it["graph"], it["held_src"], it["held_dst"], it["neg_dst"]
     assert (g.n, g.m, hs.size, it["T"]) == (gold["n"], gold["m_train"], gold["held_out"], gold["T"])
-    tr = trainer_for(g, d=it["d"], K=5, orders=2, dtype=dtype, seed=it["seed"], total_samples=it["T"])
+    tr = trainer_for(g, d=it["d"], K=5, orders=2, dtype=dtype, seed=it["seed"], total_samples=it["T"],
+                     hot_shadow=hot_shadow)
     tr.train_steps(0, it["T"])
     tr.check()
     U = tr.read(lh.LH_TABLE_U).cpu().numpy()
     C = tr.read(lh.LH_TABLE_C).cpu().numpy()
     uc = oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg))
     uu = oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
-    print(f"mid graph {dtype}: uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} (oracle {gold['auc_uu']:.4f})",
+    print(f"mid graph {dtype}{' shadow' if hot_shadow else ''}: uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} (oracle {gold['auc_uu']:.4f})",
           flush=True)
     assert abs(uc - gold["auc_uc"]) <= 0.005 and abs(uu - gold["auc_uu"]) <= 0.005
