@@ -90,9 +90,10 @@ typedef struct {
                            arc, so that a row of average traffic has at most this many
                            concurrent writers (staleness bound).  <= 0: no cap.          */
     int32_t hot_shadow; /* HOGWILD with LH_BF16 tables: 0 = hot rows take packed bfloat16
-                           atomic adds of increments rounded stochastically onto the row's
-                           bfloat16 grid (the stored value is distributed as a stochastic
-                           rounding of row + increment, as for cold rows); 1 = hot rows
+                           atomic adds of SR(row + increment) - row, SR the stochastic
+                           rounding a cold row is stored with (without a concurrent write
+                           the result is SR(row + increment) exactly while |increment| <=
+                           |row| / 2, else within one bfloat16 spacing); 1 = hot rows
                            accumulate in a binary32 shadow (one per table, up to
                            max(2^17, n/16) rows, in the workspace) for the duration of each
                            lh_train_steps launch and are rounded stochastically back into

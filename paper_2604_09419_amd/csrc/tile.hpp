@@ -212,12 +212,13 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
 //   bfloat16 table rows (id >= 0): with the random bits of unit un being
 //   lowbias32(sr + (ctr * 256 + un) * phi), a cold row is stored as the stochastic
 //   rounding SR(old + inc); a hot row receives, by packed bfloat16 atomic adds, the
-//   increments SR(old + inc) - old, which are exact multiples of the row's bfloat16 spacing
-//   (units whose increments are both zero are skipped).  Where no other write changed the
-//   unit since it was loaded, the atomic result is exactly SR(old + inc), the value a cold
-//   store would have written; otherwise the increment lands on the changed value, and the
-//   atomic unit rounds the sum where it is not representable.  Shadow rows (id < 0, even
-//   elements then odd ones) get binary32 atomic increments.
+//   increments SR(old + inc) - old rounded to nearest (units whose increments are both zero
+//   are skipped).  While old and SR(old + inc) are within a factor of two of each other
+//   (always when |inc| <= |old| / 2) that difference is exact, and where no other write
+//   changed the unit since it was loaded the atomic result is SR(old + inc) bit for bit, the
+//   value a cold store would have written; near zero it may be one bfloat16 spacing off.
+//   A concurrent change receives the increment on top.  Shadow rows (id < 0, even elements
+//   then odd ones) get binary32 atomic increments.
 template <typename TT, int LPS, int UPL>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
