@@ -225,7 +225,8 @@ __global__ void k_batch_reset(unsigned long long *queue, unsigned long long *don
 template <typename TT>
 constexpr int batch_min_waves() { return sizeof(TT) == 2 ? 4 : 3; }
 
-template <typename TT, int KMAX, int V>
+// SH: the shadow path is compiled in (a graph may keep its hot rows in a binary32 shadow).
+template <typename TT, int KMAX, int V, bool SH>
 __global__ void __launch_bounds__(256, batch_min_waves<TT>()) k_batch(BatchArgs a)
 {
     using Cfg = BatchCfg<TT, V>;
@@ -247,10 +248,10 @@ __global__ void __launch_bounds__(256, batch_min_waves<TT>()) k_batch(BatchArgs 
         if (s1 > D.limit) s1 = D.limit;
         if (g.nunits <= Cfg::LS * Cfg::US) {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LS, Cfg::US, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LS, Cfg::US, KMAX, 2, false, SH>(g, t, s1, so);
         } else {
             for (unsigned long long t = s0; t < s1; t += 64)
-                sgd_tile<TT, Cfg::LL, Cfg::UL, KMAX, 2, false>(g, t, s1, so);
+                sgd_tile<TT, Cfg::LL, Cfg::UL, KMAX, 2, false, SH>(g, t, s1, so);
         }
         if (lane == 0 && s1 > s0) atomicAdd(&a.done[lo], s1 - s0);
     }
@@ -284,22 +285,29 @@ namespace lh {
 // Resident blocks per CU and lanes per sample of the narrower tile configuration of a
 // batched kernel variant (the narrower one gives the upper bound on samples in flight, so
 // hot rows are over- rather than under-counted).
+// bfloat16 batches always run the kernel built with the shadow path, which checks per
+// graph whether a shadow is in use.  Unlike the one-graph kernel, the batched one (two tile
+// shapes, at its 128-register budget) measured slower with the path compiled out (C4
+// without shadows: 1,124 M against 1,262 M samples/s).
+
 static int batch_occupancy(const lh_batch *b, int variant, int *ls_out)
 {
     int occ = 0, ls = 8;
     const bool k5 = b->K <= 5;
-#define LH_OCC(TT, KM, V)                                                               \
-    {                                                                                   \
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<TT, KM, V>, 256, 0); \
-        ls = BatchCfg<TT, V>::LS;                                                       \
+#define LH_OCC(TT, KM, V, SH)                                                                   \
+    {                                                                                           \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<TT, KM, V, SH>, 256, 0); \
+        ls = BatchCfg<TT, V>::LS;                                                               \
     }
+#define LH_OCC_BF(KM, V) LH_OCC(uint16_t, KM, V, true)
     if (b->dtype == LH_BF16) {
-        if (k5) { if (variant == 0) LH_OCC(uint16_t, 5, 0) else LH_OCC(uint16_t, 5, 1) }
-        else { if (variant == 0) LH_OCC(uint16_t, 8, 0) else LH_OCC(uint16_t, 8, 1) }
+        if (k5) { if (variant == 0) LH_OCC_BF(5, 0) else LH_OCC_BF(5, 1) }
+        else { if (variant == 0) LH_OCC_BF(8, 0) else LH_OCC_BF(8, 1) }
     } else {
-        if (k5) { if (variant == 0) LH_OCC(float, 5, 0) else LH_OCC(float, 5, 1) }
-        else { if (variant == 0) LH_OCC(float, 8, 0) else LH_OCC(float, 8, 1) }
+        if (k5) { if (variant == 0) LH_OCC(float, 5, 0, false) else LH_OCC(float, 5, 1, false) }
+        else { if (variant == 0) LH_OCC(float, 8, 0, false) else LH_OCC(float, 8, 1, false) }
     }
+#undef LH_OCC_BF
 #undef LH_OCC
     *ls_out = ls;
     return occ < 1 ? 8 : occ;
@@ -376,20 +384,22 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
     (void)bpc;
     dim3 grid(b->grid), block(256);
     const bool k5 = b->K <= 5;
-#define LH_BL(TT, KM, V) hipLaunchKernelGGL((k_batch<TT, KM, V>), grid, block, 0, s, a)
+#define LH_BL(TT, KM, V, SH) hipLaunchKernelGGL((k_batch<TT, KM, V, SH>), grid, block, 0, s, a)
+#define LH_BL_BF(KM, V) { LH_BL(uint16_t, KM, V, true); }
     if (b->dtype == LH_BF16) {
         if (k5) {
-            if (variant == 0) LH_BL(uint16_t, 5, 0); else LH_BL(uint16_t, 5, 1);
+            if (variant == 0) LH_BL_BF(5, 0) else LH_BL_BF(5, 1)
         } else {
-            if (variant == 0) LH_BL(uint16_t, 8, 0); else LH_BL(uint16_t, 8, 1);
+            if (variant == 0) LH_BL_BF(8, 0) else LH_BL_BF(8, 1)
         }
     } else {
         if (k5) {
-            if (variant == 0) LH_BL(float, 5, 0); else LH_BL(float, 5, 1);
+            if (variant == 0) LH_BL(float, 5, 0, false); else LH_BL(float, 5, 1, false);
         } else {
-            if (variant == 0) LH_BL(float, 8, 0); else LH_BL(float, 8, 1);
+            if (variant == 0) LH_BL(float, 8, 0, false); else LH_BL(float, 8, 1, false);
         }
     }
+#undef LH_BL_BF
 #undef LH_BL
     hipError_t e = hipGetLastError();
     for (int i = 0; i < b->G && e == hipSuccess; ++i) {

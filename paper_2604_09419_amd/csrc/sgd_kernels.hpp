@@ -17,7 +17,8 @@ namespace lh {
 template <typename TT>
 constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 5 : 3; }
 
-template <typename TT, int LPS, int UPL, int KMAX, int ORD>
+// SH: bfloat16 tables whose hot rows live in a binary32 shadow for the launch.
+template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SH>
 __global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)
 {
     const unsigned wpb = blockDim.x >> 6;
@@ -26,7 +27,7 @@ __global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphD
     unsigned long long ntiles = (end - first + 63) / 64;
     SnapOut so{};
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, UPL, KMAX, ORD, false>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, UPL, KMAX, ORD, false, SH>(g, first + t * 64, end, so);
 }
 
 template <typename TT, int LPS, int UPL, int KMAX, int ORD>
@@ -38,7 +39,7 @@ __global__ void __launch_bounds__(256) k_snap_contrib(GraphDev g, unsigned long 
     unsigned long long nw = (unsigned long long)gridDim.x * wpb;
     unsigned long long ntiles = (end - first + 63) / 64;
     for (unsigned long long t = wave; t < ntiles; t += nw)
-        sgd_tile<TT, LPS, UPL, KMAX, ORD, true>(g, first + t * 64, end, so);
+        sgd_tile<TT, LPS, UPL, KMAX, ORD, true, false>(g, first + t * 64, end, so);
 }
 
 inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_per_cu)
@@ -146,34 +147,52 @@ hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c
     return e;
 }
 
-// Samples a Hogwild launch of `count` samples would keep in flight (0: no such kernel).
-template <typename TT, int ORD>
-double hogwild_in_flight_t(const GraphDev &g, const TileCfg &c, unsigned long long count, int num_cu)
+// Samples a Hogwild launch of `count` samples would keep in flight (0: no such kernel);
+// g.slot set means the kernel with the binary32 shadow (bfloat16 only).
+template <typename TT, int ORD, bool SH>
+double hogwild_in_flight_sh(const GraphDev &g, const TileCfg &c, unsigned long long count, int num_cu)
 {
     unsigned grid = 0;
-#define LH_PLAN_H(L, C)                                                                     \
-    if (c.lps == L && c.upl == C)                                                           \
-        return plan_launch(g.K <= 5 ? k_hogwild<TT, L, C, 5, ORD> : k_hogwild<TT, L, C, 8, ORD>, L, g, c, count, \
-                           num_cu, &grid);
+#define LH_PLAN_H(L, C)                                                                                  \
+    if (c.lps == L && c.upl == C)                                                                        \
+        return plan_launch(g.K <= 5 ? k_hogwild<TT, L, C, 5, ORD, SH> : k_hogwild<TT, L, C, 8, ORD, SH>, L, g, c, \
+                           count, num_cu, &grid);
     LH_CFG_LIST(LH_PLAN_H)
 #undef LH_PLAN_H
     return 0.0;
 }
 
 template <typename TT, int ORD>
-hipError_t launch_hogwild_t(const GraphDev &g, const TileCfg &c, unsigned long long first, unsigned long long end,
-                            int num_cu, const ShadowCtx *sc, hipStream_t s)
+double hogwild_in_flight_t(const GraphDev &g, const TileCfg &c, unsigned long long count, int num_cu)
+{
+    if constexpr (sizeof(TT) == 2)
+        if (g.slot) return hogwild_in_flight_sh<TT, ORD, true>(g, c, count, num_cu);
+    return hogwild_in_flight_sh<TT, ORD, false>(g, c, count, num_cu);
+}
+
+template <typename TT, int ORD, bool SH>
+hipError_t launch_hogwild_sh(const GraphDev &g, const TileCfg &c, unsigned long long first, unsigned long long end,
+                             int num_cu, const ShadowCtx *sc, hipStream_t s)
 {
     const bool k5 = g.K <= 5;
-#define LH_LAUNCH_H(L, C)                                                 \
-    if (c.lps == L && c.upl == C) {                                       \
-        if (k5)                                                           \
-            return launch_one(k_hogwild<TT, L, C, 5, ORD>, L, g, c, first, end, num_cu, sc, s); \
-        return launch_one(k_hogwild<TT, L, C, 8, ORD>, L, g, c, first, end, num_cu, sc, s);     \
+#define LH_LAUNCH_H(L, C)                                                                        \
+    if (c.lps == L && c.upl == C) {                                                              \
+        if (k5) return launch_one(k_hogwild<TT, L, C, 5, ORD, SH>, L, g, c, first, end, num_cu, sc, s); \
+        return launch_one(k_hogwild<TT, L, C, 8, ORD, SH>, L, g, c, first, end, num_cu, sc, s);        \
     }
     LH_CFG_LIST(LH_LAUNCH_H)
 #undef LH_LAUNCH_H
     return hipErrorInvalidConfiguration;
+}
+
+// A shadow context selects the kernel built with the shadow path (bfloat16 only).
+template <typename TT, int ORD>
+hipError_t launch_hogwild_t(const GraphDev &g, const TileCfg &c, unsigned long long first, unsigned long long end,
+                            int num_cu, const ShadowCtx *sc, hipStream_t s)
+{
+    if constexpr (sizeof(TT) == 2)
+        if (sc) return launch_hogwild_sh<TT, ORD, true>(g, c, first, end, num_cu, sc, s);
+    return launch_hogwild_sh<TT, ORD, false>(g, c, first, end, num_cu, nullptr, s);
 }
 
 template <typename TT, int ORD>

@@ -151,13 +151,14 @@ __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint
 // the row and then the odd ones, element 2 un + e at e * d / 2 + un, so the lanes of a
 // group touch contiguous words for each half).  The address is chosen without a branch
 // and nothing here uses the loaded words, so every row's loads of a sample are in flight
-// together; shadow rows are packed afterwards by pack_shadow_row.
-template <typename TT, int LPS, int UPL>
+// together; shadow rows are packed afterwards by pack_shadow_row.  SH: the kernel may meet
+// shadow rows (else ids are never negative and hi stays untouched).
+template <typename TT, int LPS, int UPL, bool SH>
 __device__ __forceinline__ void load_row_raw(const GraphDev &g, int t, int id, int gl, uint32_t (&lo)[UPL],
                                              uint32_t (&hi)[UPL])
 {
     const int nu = g.nunits;
-    if constexpr (sizeof(TT) == 4) {
+    if constexpr (sizeof(TT) == 4 || !SH) {
         load_row<TT, LPS, UPL>((const TT *)g.tab[t] + (long long)id * g.d, nu, gl, lo);
     } else {
         const bool sh = id < 0;
@@ -174,10 +175,10 @@ __device__ __forceinline__ void load_row_raw(const GraphDev &g, int t, int id, i
 }
 
 // bfloat16: a shadow row's words become units rounded to nearest even (no-op otherwise).
-template <typename TT, int UPL>
+template <typename TT, int UPL, bool SH>
 __device__ __forceinline__ void pack_shadow_row(int id, uint32_t (&lo)[UPL], const uint32_t (&hi)[UPL])
 {
-    if constexpr (sizeof(TT) == 2) {
+    if constexpr (sizeof(TT) == 2 && SH) {
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const uint32_t p = f32_to_bf16_rne(__uint_as_float(lo[k])) | (f32_to_bf16_rne(__uint_as_float(hi[k])) << 16);
@@ -186,25 +187,25 @@ __device__ __forceinline__ void pack_shadow_row(int id, uint32_t (&lo)[UPL], con
     }
 }
 
-template <typename TT, int LPS, int UPL, int KMAX>
+template <typename TT, int LPS, int UPL, int KMAX, bool SH>
 __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, int tA, int tB, int u,
                                           const int (&ids)[KMAX + 1], int K, int gl)
 {
     uint32_t ah[UPL], bh[KMAX + 1][UPL];
-    load_row_raw<TT, LPS, UPL>(g, tA, u, gl, r.a, ah);
+    load_row_raw<TT, LPS, UPL, SH>(g, tA, u, gl, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j <= K) {
-            load_row_raw<TT, LPS, UPL>(g, tB, ids[j], gl, r.b[j], bh[j]);
+            load_row_raw<TT, LPS, UPL, SH>(g, tB, ids[j], gl, r.b[j], bh[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < UPL; ++k) r.b[j][k] = bh[j][k] = 0u;
         }
     }
-    pack_shadow_row<TT, UPL>(u, r.a, ah);
+    pack_shadow_row<TT, UPL, SH>(u, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j)
-        if (j <= K) pack_shadow_row<TT, UPL>(ids[j], r.b[j], bh[j]);
+        if (j <= K) pack_shadow_row<TT, UPL, SH>(ids[j], r.b[j], bh[j]);
 }
 
 // Write one row back: new = old + inc.  `hot` asks for the atomic path.
@@ -219,7 +220,7 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
 //   value a cold store would have written; near zero it may be one bfloat16 spacing off.
 //   A concurrent change receives the increment on top.  Shadow rows (id < 0, even elements
 //   then odd ones) get binary32 atomic increments.
-template <typename TT, int LPS, int UPL>
+template <typename TT, int LPS, int UPL, bool SH>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
                                           uint32_t ctr)
@@ -227,7 +228,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
     constexpr int EPU = Elem<TT>::EPU;
     const int nunits = g.nunits;
     if constexpr (EPU == 2) {
-        if (id < 0) {
+        if (SH && id < 0) {
             float *sw = g.shadow[t] + (long long)(~id) * g.d;
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
@@ -291,7 +292,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 // the context rows (the same table for first order).  ids[0] = v, ids[1..K] = negatives
 // (bfloat16 Hogwild: ~slot for rows in the shadow).  hot: bit 0 for the vertex row,
 // bit 1 + j for slot j.
-template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP>
+template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP, bool SH>
 __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&ids)[KMAX + 1], int K, float eta,
                                           unsigned dupb, unsigned dupu, unsigned hot, uint32_t sr, int oi, int gl,
                                           const SnapOut &so, unsigned long long s, int tabA, int tabB,
@@ -385,7 +386,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         unsigned atom = hot | (dupb << 1);
         if constexpr (FIRST) atom |= (dupu << 1) | (dupu ? 1u : 0u);
         // vertex row
-        write_row<TT, LPS, UPL>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
+        write_row<TT, LPS, UPL, SH>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
@@ -395,14 +396,16 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
             for (int k = 0; k < UPL; ++k)
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) inc[k][e] = gj[j] * val<TT>(a[k], e) - el * val<TT>(b[j][k], e);
-            write_row<TT, LPS, UPL>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0, sr,
+            write_row<TT, LPS, UPL, SH>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0, sr,
                                     (uint32_t)(oi * (KMAX + 2) + 1 + j));
         }
     }
 }
 
-// One tile of 64 samples [tile, min(tile + 64, end)).  UPL units per lane.
-template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SNAP>
+// One tile of 64 samples [tile, min(tile + 64, end)).  UPL units per lane.  SH: bfloat16
+// Hogwild with a binary32 shadow of the hot rows (compiled out otherwise: the shadow's
+// address choice and second-half loads cost a quarter of the kernel's speed even unused).
+template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SNAP, bool SH>
 __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long tile, unsigned long long end,
                                          const SnapOut &so)
 {
@@ -478,7 +481,7 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
             // bfloat16 Hogwild with a shadow: the rows with a shadow slot are this launch's
             // hot rows; their ids become ~slot (negative, so equal rows stay equal and never
             // meet a table id).
-            if constexpr (sizeof(TT) == 2 && !SNAP) {
+            if constexpr (sizeof(TT) == 2 && !SNAP && SH) {
                 if (g.slot) {
                     my_hot = 0;
                     int sl[KMAX + 2];
@@ -520,17 +523,17 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
         // 2 (2 + K) rows per sample are in flight at once.
         Rows<TT, UPL, KMAX> r2, r1;
         if constexpr ((ORD & 2) != 0)
-            load_rows<TT, LPS, UPL, KMAX>(r2, g, LH_TABLE_U, LH_TABLE_C, u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX, SH>(r2, g, LH_TABLE_U, LH_TABLE_C, u, ids, K, gl);
         if constexpr ((ORD & 1) != 0)
-            load_rows<TT, LPS, UPL, KMAX>(r1, g, LH_TABLE_U1, LH_TABLE_U1, u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX, SH>(r1, g, LH_TABLE_U1, LH_TABLE_U1, u, ids, K, gl);
         int oi = 0;
         if constexpr ((ORD & 2) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, false, SNAP>(g, u, ids, K, eta, dupb, dupu, hot, sr, oi, gl, so, s,
+            sgd_order<TT, LPS, UPL, KMAX, false, SNAP, SH>(g, u, ids, K, eta, dupb, dupu, hot, sr, oi, gl, so, s,
                                                        LH_TABLE_U, LH_TABLE_C, r2);
             ++oi;
         }
         if constexpr ((ORD & 1) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, true, SNAP>(g, u, ids, K, eta, dupb, dupu, hot, sr ^ 0x5bd1e995u, oi, gl,
+            sgd_order<TT, LPS, UPL, KMAX, true, SNAP, SH>(g, u, ids, K, eta, dupb, dupu, hot, sr ^ 0x5bd1e995u, oi, gl,
                                                       so, s, LH_TABLE_U1, LH_TABLE_U1, r1);
         }
     }
