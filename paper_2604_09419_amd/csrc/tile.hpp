@@ -98,6 +98,29 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
+// Phase B's read of a sample's value from the phase-A lane src that drew it: with one sample
+// per wavefront src is uniform and the value is read into a scalar register (the sample's
+// row addresses are then computed by the scalar unit); otherwise a cross-lane permute.
+template <int LPS>
+__device__ __forceinline__ int sample_lane(int v, int src)
+{
+    if constexpr (LPS == 64) return __builtin_amdgcn_readlane(v, src);
+    else return __shfl(v, src);
+}
+
+// Lane j's value of this lane's group of LPS lanes (j < LPS): a scalar read when the group
+// is the whole wavefront, a cross-lane permute otherwise.
+template <int LPS>
+__device__ __forceinline__ float group_lane(float x, int j)
+{
+    if constexpr (LPS == 64) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+    } else {
+        const int base = (int)(threadIdx.x & 63u) & ~(LPS - 1);
+        return __shfl(x, base + j);
+    }
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -208,10 +231,22 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
         if (j <= K) pack_shadow_row<TT, UPL, SH>(ids[j], r.b[j], bh[j]);
 }
 
+// Stochastic-rounding bits of unit un of a row: a Weyl step from the row's seed and one
+// xor-shift, full-rate integer operations only (the 32-bit multiplies of a hash run at a
+// quarter of the rate, and this kernel is bound by its vector instruction issue).  The
+// row seeds of a sample come from one lowbias32 hash per sample and order (sgd_order); any
+// fixed function of a uniformly distributed seed keeps every rounding unbiased.  The bits
+// depend on the unit, not on the lane holding it, so every tile shape rounds alike.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t rseed, int un)
+{
+    const uint32_t x = rseed + (uint32_t)un * 0x9E3779B9u;
+    return x ^ (x >> 16);
+}
+
 // Write one row back: new = old + inc.  `hot` asks for the atomic path.
 //   binary32: stored, or atomic increments;
 //   bfloat16 table rows (id >= 0): with the random bits of unit un being
-//   lowbias32(sr + (ctr * 256 + un) * phi), a cold row is stored as the stochastic
+//   mix(rseed + un * phi), mix(x) = x ^ (x >> 16), a cold row is stored as the stochastic
 //   rounding SR(old + inc); a hot row receives, by packed bfloat16 atomic adds, the
 //   increments SR(old + inc) - old rounded to nearest (units whose increments are both zero
 //   are skipped).  While old and SR(old + inc) are within a factor of two of each other
@@ -222,8 +257,7 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
 //   then odd ones) get binary32 atomic increments.
 template <typename TT, int LPS, int UPL, bool SH>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
-                                          const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t sr,
-                                          uint32_t ctr)
+                                          const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t rseed)
 {
     constexpr int EPU = Elem<TT>::EPU;
     const int nunits = g.nunits;
@@ -248,7 +282,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
             for (int k = 0; k < UPL; ++k) {
                 const int un = k * LPS + gl;
                 if (un < nunits) {
-                    const uint32_t rnd = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
+                    const uint32_t rnd = sr_bits(rseed, un);
                     uint32_t p = 0u;
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
@@ -275,7 +309,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) x[e] = val<TT>(old[k], e) + inc[k][e];
                 uint32_t rnd = 0u;
-                if constexpr (EPU == 2) rnd = lowbias32(sr + (ctr * 256u + (uint32_t)un) * 0x9E3779B9u);
+                if constexpr (EPU == 2) rnd = sr_bits(rseed, un);
                 store_coherent(w + un, f32_to_unit<TT>(x, rnd));
             }
         }
@@ -320,11 +354,24 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
     }
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) gj[j] = group_sum<LPS>(gj[j]);
+    if constexpr (LPS > KMAX) {
+        // Every lane of the group holds all 1 + K dot products: lane gl takes slot gl's
+        // sigmoid (one exp and one reciprocal per lane instead of 1 + K), and the step
+        // sizes are then read back from lanes 0..K of the group.
+        float xs = gj[0];
 #pragma unroll
-    for (int j = 0; j <= KMAX; ++j) {
-        float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-gj[j]));
-        float gg = j == 0 ? eta * (1.0f - sg) : -eta * g.alpha * sg;
-        gj[j] = j <= K ? gg : 0.f;
+        for (int j = 1; j <= KMAX; ++j) xs = gl == j ? gj[j] : xs;
+        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-xs));
+        const float gg = gl == 0 ? eta * (1.0f - sg) : -eta * g.alpha * sg;
+#pragma unroll
+        for (int j = 0; j <= KMAX; ++j) gj[j] = j <= K ? group_lane<LPS>(gg, j) : 0.f;
+    } else {
+#pragma unroll
+        for (int j = 0; j <= KMAX; ++j) {
+            float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-gj[j]));
+            float gg = j == 0 ? eta * (1.0f - sg) : -eta * g.alpha * sg;
+            gj[j] = j <= K ? gg : 0.f;
+        }
     }
     const float el = eta * g.lambda;
 
@@ -385,8 +432,13 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         // the rows as they were before the sample, so the row receives their sum.
         unsigned atom = hot | (dupb << 1);
         if constexpr (FIRST) atom |= (dupu << 1) | (dupu ? 1u : 0u);
+        // bfloat16: the sample's seed for this order; slot q's row uses seed + (q + 1) c
+        uint32_t seed = 0u;
+        if constexpr (EPU == 2) seed = lowbias32(sr);
+        constexpr uint32_t kSlot = 0x632BE59Bu;
+        (void)oi;
         // vertex row
-        write_row<TT, LPS, UPL, SH>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, sr, (uint32_t)(oi * (KMAX + 2)));
+        write_row<TT, LPS, UPL, SH>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, seed + kSlot);
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
@@ -396,8 +448,8 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
             for (int k = 0; k < UPL; ++k)
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) inc[k][e] = gj[j] * val<TT>(a[k], e) - el * val<TT>(b[j][k], e);
-            write_row<TT, LPS, UPL, SH>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0, sr,
-                                    (uint32_t)(oi * (KMAX + 2) + 1 + j));
+            write_row<TT, LPS, UPL, SH>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0,
+                                        seed + (uint32_t)(j + 2) * kSlot);
         }
     }
 }
@@ -506,16 +558,17 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
     // ---- phase B: LPS lanes per sample ----------------------------------------
     for (int r = 0; r < LPS; ++r) {
         const int src = r * GPW + grp;
-        const int u = __shfl(my_u, src);
+        const int u = sample_lane<LPS>(my_u, src);
         int ids[KMAX + 1];
 #pragma unroll
-        for (int j = 0; j <= KMAX; ++j) ids[j] = __shfl(my_ids[j], src);
-        const unsigned dup = (unsigned)__shfl((int)my_dup, src);
+        for (int j = 0; j <= KMAX; ++j) ids[j] = sample_lane<LPS>(my_ids[j], src);
+        const unsigned dup = (unsigned)sample_lane<LPS>((int)my_dup, src);
         unsigned hot = 0;
         uint32_t sr = 0;
-        if constexpr (!SNAP) hot = (unsigned)__shfl((int)my_hot, src);
-        if constexpr (sizeof(TT) == 2 && !SNAP) sr = (uint32_t)__shfl((int)my_sr, src);
-        const float eta = __shfl(my_eta, src);  // every cross-lane read before lanes diverge
+        if constexpr (!SNAP) hot = (unsigned)sample_lane<LPS>((int)my_hot, src);
+        if constexpr (sizeof(TT) == 2 && !SNAP) sr = (uint32_t)sample_lane<LPS>((int)my_sr, src);
+        // every cross-lane read before lanes diverge
+        const float eta = __int_as_float(sample_lane<LPS>(__float_as_int(my_eta), src));
         const unsigned long long s = tile + (unsigned long long)src;
         if (s >= end) continue;
         const unsigned dupb = dup & 0xffffu, dupu = dup >> 16;
