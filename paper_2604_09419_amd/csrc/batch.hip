@@ -219,15 +219,16 @@ __global__ void k_batch_reset(unsigned long long *queue, unsigned long long *don
     for (int g = i; g < G; g += blockDim.x) done[g] = 0ull;
 }
 
-// Register budget of the batched kernel: at least 3 (binary32) or 4 (bfloat16) waves per
-// SIMD.  Unlike the one-graph kernel, bfloat16 measured 21 % slower at 5 waves (C4: 990 M
-// against 1,260 M samples/s).
-template <typename TT>
-constexpr int batch_min_waves() { return sizeof(TT) == 2 ? 4 : 3; }
+// Register budget of the batched kernel (it holds two tile shapes): at least 3 waves per
+// SIMD, or 4 for bfloat16 with the shadow path.  Measured on C4 (bfloat16): without the
+// shadow path 3 waves (no spills) ran 1,785 M samples/s against 1,124 M at 4 waves (with
+// spills); with the path 4 waves ran 1,262 M against 1,084 M at 3 and 990 M at 5.
+template <typename TT, bool SH>
+constexpr int batch_min_waves() { return sizeof(TT) == 2 && SH ? 4 : 3; }
 
 // SH: the shadow path is compiled in (a graph may keep its hot rows in a binary32 shadow).
 template <typename TT, int KMAX, int V, bool SH>
-__global__ void __launch_bounds__(256, batch_min_waves<TT>()) k_batch(BatchArgs a)
+__global__ void __launch_bounds__(256, (batch_min_waves<TT, SH>())) k_batch(BatchArgs a)
 {
     using Cfg = BatchCfg<TT, V>;
     const int lane = threadIdx.x & 63;
@@ -285,21 +286,26 @@ namespace lh {
 // Resident blocks per CU and lanes per sample of the narrower tile configuration of a
 // batched kernel variant (the narrower one gives the upper bound on samples in flight, so
 // hot rows are over- rather than under-counted).
-// bfloat16 batches always run the kernel built with the shadow path, which checks per
-// graph whether a shadow is in use.  Unlike the one-graph kernel, the batched one (two tile
-// shapes, at its 128-register budget) measured slower with the path compiled out (C4
-// without shadows: 1,124 M against 1,262 M samples/s).
+// Whether some graph of the batch keeps its hot rows in a binary32 shadow: then the kernel
+// built with the shadow path runs (it checks per graph whether a shadow is in use).
+static bool batch_shadow(const lh_batch *b)
+{
+    for (const lh_handle *h : b->hs)
+        if (uses_shadow(h->p)) return true;
+    return false;
+}
+
 
 static int batch_occupancy(const lh_batch *b, int variant, int *ls_out)
 {
     int occ = 0, ls = 8;
-    const bool k5 = b->K <= 5;
+    const bool k5 = b->K <= 5, sh = batch_shadow(b);
 #define LH_OCC(TT, KM, V, SH)                                                                   \
     {                                                                                           \
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<TT, KM, V, SH>, 256, 0); \
         ls = BatchCfg<TT, V>::LS;                                                               \
     }
-#define LH_OCC_BF(KM, V) LH_OCC(uint16_t, KM, V, true)
+#define LH_OCC_BF(KM, V) { if (sh) LH_OCC(uint16_t, KM, V, true) else LH_OCC(uint16_t, KM, V, false) }
     if (b->dtype == LH_BF16) {
         if (k5) { if (variant == 0) LH_OCC_BF(5, 0) else LH_OCC_BF(5, 1) }
         else { if (variant == 0) LH_OCC_BF(8, 0) else LH_OCC_BF(8, 1) }
@@ -383,9 +389,9 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a.queue, a.done, b->G);
     (void)bpc;
     dim3 grid(b->grid), block(256);
-    const bool k5 = b->K <= 5;
+    const bool k5 = b->K <= 5, sh = batch_shadow(b);
 #define LH_BL(TT, KM, V, SH) hipLaunchKernelGGL((k_batch<TT, KM, V, SH>), grid, block, 0, s, a)
-#define LH_BL_BF(KM, V) { LH_BL(uint16_t, KM, V, true); }
+#define LH_BL_BF(KM, V) { if (sh) LH_BL(uint16_t, KM, V, true); else LH_BL(uint16_t, KM, V, false); }
     if (b->dtype == LH_BF16) {
         if (k5) {
             if (variant == 0) LH_BL_BF(5, 0) else LH_BL_BF(5, 1)
