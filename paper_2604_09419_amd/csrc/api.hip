@@ -51,6 +51,7 @@ GraphDev graph_dev(const lh_handle *h)
     const bool shadowed = shadow_ctx(h, &sc);
     for (int t = 0; t < 3; ++t) g.shadow[t] = shadowed ? sc.shadow[t] : nullptr;
     g.slot = shadowed ? sc.slot : nullptr;
+    g.tiles = h->ws ? (unsigned long long *)(h->ws + h->lay.tiles) : nullptr;
     return g;
 }
 

@@ -32,6 +32,9 @@ struct GraphDev {
     // for binary32 tables and SNAPSHOT.
     float *shadow[3];
     const int32_t *slot;
+    // Hogwild: the launch's tile counter (device word, reset to 0 before each launch);
+    // wavefronts take 64-sample tiles from it until none are left.
+    unsigned long long *tiles;
 };
 
 // A kernel configuration: lanes per sample, 4-byte units of a row per lane (a unit is one
@@ -41,7 +44,7 @@ struct TileCfg {
 };
 
 struct WsLayout {
-    size_t status = 0, erec = 0, nrec = 0;
+    size_t status = 0, tiles = 0, erec = 0, nrec = 0;
     size_t nheat = 0;                                   // [n] bytes: per-node heat
     size_t slot = 0, srows = 0, shadow = 0;             // bfloat16 Hogwild shadow (else 0)
     long long shadow_cap = 0;                           // shadow rows per table

@@ -28,6 +28,7 @@ WsLayout ws_layout(const lh_params &p, long long n, long long m)
     WsLayout L;
     size_t off = 0;
     L.status = carve(off, 256);
+    L.tiles = carve(off, 256);
     L.erec = carve(off, sizeof(EdgeRec) * (size_t)(m > 0 ? m : 1));
     L.nrec = carve(off, sizeof(NegRec) * (size_t)(n > 0 ? n : 1));
     L.nheat = carve(off, (size_t)(n > 0 ? n : 1));

@@ -17,17 +17,31 @@ namespace lh {
 template <typename TT>
 constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 5 : 3; }
 
-// SH: bfloat16 tables whose hot rows live in a binary32 shadow for the launch.
+// SH: bfloat16 tables whose hot rows live in a binary32 shadow for the launch.  Each
+// wavefront takes 64-sample tiles from the launch's tile counter (g.tiles, zero at launch)
+// until none are left, so wavefronts that meet slow rows do not hold up a fixed share of
+// the work and the grid is only as large as what is resident.
 template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SH>
 __global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)
 {
-    const unsigned wpb = blockDim.x >> 6;
-    unsigned long long wave = (unsigned long long)blockIdx.x * wpb + (threadIdx.x >> 6);
-    unsigned long long nw = (unsigned long long)gridDim.x * wpb;
-    unsigned long long ntiles = (end - first + 63) / 64;
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned long long ntiles = (end - first + 63) / 64;
     SnapOut so{};
-    for (unsigned long long t = wave; t < ntiles; t += nw)
+    while (true) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(g.tiles, 1ull);
+        t = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
+            (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(t & 0xffffffffull));
+        if (t >= ntiles) break;
         sgd_tile<TT, LPS, UPL, KMAX, ORD, false, SH>(g, first + t * 64, end, so);
+    }
+}
+
+// Zero a launch's tile counter (a kernel, not a memset, so the launch can be captured).
+template <int N>
+__global__ void k_zero_tiles(unsigned long long *c)
+{
+    if (threadIdx.x < N) c[threadIdx.x] = 0ull;
 }
 
 template <typename TT, int LPS, int UPL, int KMAX, int ORD>
@@ -50,6 +64,15 @@ inline unsigned hogwild_grid(unsigned long long count, int num_cu, int blocks_pe
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return (unsigned)blocks;
+}
+
+// Resident workgroups of a kernel on the device (at least 1 per CU).
+template <typename KernelT>
+inline unsigned resident_blocks(KernelT kernel, int num_cu)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) != hipSuccess || occ < 1) occ = 1;
+    return (unsigned)num_cu * (unsigned)occ;
 }
 
 // Heat threshold for a launch whose rows are exposed to a window of W samples (those in
@@ -113,7 +136,7 @@ template <typename KernelT>
 inline double plan_launch(KernelT kern, int lps, const GraphDev &g, const TileCfg &c, unsigned long long count,
                           int num_cu, unsigned *grid_out)
 {
-    unsigned grid = hogwild_grid(count, num_cu, c.blocks_per_cu);
+    unsigned grid = std::min(hogwild_grid(count, num_cu, c.blocks_per_cu), resident_blocks(kern, num_cu));
     double F = samples_in_flight(kern, grid, num_cu, lps);
     if (g.max_in_flight > 0.0 && F > g.max_in_flight) {
         double per_block = 4.0 * (64.0 / lps);
@@ -141,6 +164,8 @@ hipError_t launch_one(KernelT kern, int lps, const GraphDev &g, const TileCfg &c
     } else {
         gl.slot = nullptr;
     }
+    if (!gl.tiles) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_tiles<1>, dim3(1), dim3(64), 0, s, gl.tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, gl, first, end);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && sc) e = shadow_end(*sc, gl.hot_heat, first, s);
