@@ -10,10 +10,9 @@
 
 namespace lh {
 
-// Grid-stride over 64-sample tiles: wave w takes tiles w, w + W, w + 2W, ...  The register
-// budget is capped for at least 3 (binary32) or 5 (bfloat16) waves per SIMD.  The bfloat16
-// kernel is latency bound: 5 waves (96 registers, no spills) measured 2 % faster than 4
-// on both hub-heavy and large uniform tables, and 6 (with spills) slower.
+// Register budget of the one-graph kernel: at least 3 (binary32) or 5 (bfloat16) waves per
+// SIMD.  The bfloat16 kernel is latency bound: 5 waves (96 registers, no spills) measured
+// 2 % faster than 4 on both hub-heavy and large uniform tables, and 6 (with spills) slower.
 template <typename TT>
 constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 5 : 3; }
 
