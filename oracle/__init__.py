@@ -38,10 +38,16 @@ _lib = None
 
 
 def lib():
+    """The oracle's shared library.  ``LH_ORACLE_SO`` names another build of the same
+    source to load instead (the tests use it to run a pin against a copy of the oracle
+    with a deliberately planted mistake)."""
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_SO)
+        path = os.environ.get("LH_ORACLE_SO")
+        if not path:
+            build()
+            path = _SO
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, u64, u32, i32, f64 = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                    ctypes.c_int, ctypes.c_double)
@@ -53,6 +59,7 @@ def lib():
         L.or_alias_build.argtypes = [P, i64, P, P]
         L.or_alias_build.restype = i32
         L.or_sample.argtypes = [i64, i64, P, P, P, P, P, P, u64, u32, i32, u64, u64, P, P, P]
+        L.or_sample_negatives.argtypes = [i64, P, P, u64, u32, i32, u64, u64, P]
         L.or_init_table.argtypes = [P, i32, i64, i32, u64, u32]
         L.or_train.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
                                f64, f64, f64, u64, P, P, P, u64, u64, i32, u64]
@@ -174,6 +181,19 @@ def sample(t: Tables, seed: int, graph_id: int, K: int, first: int, count: int):
     lib().or_sample(t.n, t.m, _p(t.src), _p(t.dst), _p(t.ethr), _p(t.ealias), _p(t.nthr),
                     _p(t.nalias), seed, graph_id, K, first, count, _p(u), _p(v), _p(neg))
     return u, v, neg[: count * K].reshape(count, K)
+
+
+def sample_negatives(n: int, nthr, nalias, seed: int, graph_id: int, K: int, first: int,
+                     count: int) -> np.ndarray:
+    """Negatives (count x K) of sample indices [first, first+count) from a negative table
+    alone: slot j of sample s draws from Block(key = (seed, graph_id), ctr = (s, j, 0, 0))
+    exactly as ``sample`` does (Algorithm 1, v- ~ q of Eq. (1))."""
+    nthr = _c(nthr, np.uint64)
+    nalias = _c(nalias, np.int32)
+    assert nthr.size == n and nalias.size == n
+    neg = np.zeros(count * max(K, 1), dtype=np.int32)
+    lib().or_sample_negatives(n, _p(nthr), _p(nalias), seed, graph_id, K, first, count, _p(neg))
+    return neg[: count * K].reshape(count, K)
 
 
 def init_table(t: int, rows: int, d: int, seed: int, graph_id: int) -> np.ndarray:

@@ -299,6 +299,21 @@ void or_sample(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
         draw_tuple(&g, first + i, &u[i], &v[i], &neg[i * (uint64_t)K]);
 }
 
+/* The negatives alone (a negative table needs no arcs): slot j = 1..K of sample s
+ * from the same blocks as draw_tuple. */
+void or_sample_negatives(int64_t n, const uint64_t *nthr, const int32_t *nalias,
+                         uint64_t seed, uint32_t graph_id, int K,
+                         uint64_t first, uint64_t count, int32_t *neg)
+{
+    for (uint64_t i = 0; i < count; i++) {
+        for (int j = 1; j <= K; j++) {
+            uint64_t ctr[4] = {first + i, (uint64_t)j, 0, 0}, x[4];
+            or_philox4x64_10(seed, (uint64_t)graph_id, ctr, x);
+            neg[i * (uint64_t)K + (uint64_t)(j - 1)] = (int32_t)draw(nthr, nalias, n, x[0], x[1]);
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Initial embeddings: uniform on [-0.5/d, 0.5/d).  Element (t, r, c) of table  */
 /* t (0 = U, 1 = C, 2 = U1) is word c mod 4 of Block(key = (seed, 2^32 | g),    */
