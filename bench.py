@@ -1,19 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of LINE edge-sampled SGD on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload C2]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload C2]
 
 One step = the whole hot path over the workload's synthetic graph, arcs already in HBM:
 validate the arcs and count out-degrees, build both alias tables (binary64 normalisation
 and prefix sums), initialise the embedding tables, then train all T edge samples (Philox
 draws, row gathers, dot products, scatter updates) with the Hogwild kernel.  ``value`` is
-T / (mean step time) in edge samples per second.
+T / (median step time) in edge samples per second.
 
 Default workload (C2): directed R-MAT scale 20 (2^20 nodes, 2^24 unique arcs, 1 % held
 out), lognormal(0, 1) weights, d = 128, K = 5, first + second order, binary32 tables,
 T = 2e8, eta 0.025 decaying linearly to 0.  After the timed steps the same hot path runs
 with bfloat16 tables (C3) for the BF16-over-FP32 speedup, and the held-out AUC of both
-is compared with the binary64 oracle's.
+is compared with the binary64 oracle's.  The C3 embedding error is measured on the first
+2^20 samples in SNAPSHOT mode against the oracle's binary64 SNAPSHOT run.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
@@ -129,8 +130,7 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False
                  eta0=cfg["eta0"], seed=seed, total_samples=T, build=False, init=False, hot_shadow=hot_shadow)
     # Tuning happens once, outside the timed region, with the step size scaled to zero.
     tr.build_alias()
-    if dtype == "fp32":  # bfloat16 timing runs are switched off in the library for now
-        tr.tune(probe=min(T, 20_000_000), cache_path=tune_cache)
+    tr.tune(probe=min(T, 20_000_000), cache_path=tune_cache)
     step_ms, kern_ms = [], []
     for i in range(warmup + steps):
         torch.cuda.synchronize()
@@ -181,12 +181,29 @@ def held_out_auc(tr, hs, hd, neg, orders):
     return out
 
 
+def host_threads():
+    """Threads for the oracle's CPU legs: every core in this process's affinity mask, or
+    fewer when OMP_NUM_THREADS says so (a GPU machine gives one GPU's job a fixed share of
+    its cores that way).  Returns (threads, affinity core count, reason for a cap)."""
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and 0 < int(omp) < cores:
+        return int(omp), cores, f"OMP_NUM_THREADS={omp} (the host's share for this job)"
+    return cores, cores, ""
+
+
+def median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
+
+
 def cpu_baseline(cfg, g, seed, target_s=15.0):
     """The oracle's binary32 Hogwild mode on the host cores, on a bounded prefix of the
     same sample stream."""
     import numpy as np
     import oracle
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    threads, cores, cap = host_threads()
     t0 = time.time()
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
     d, K, orders, T = cfg["d"], cfg["K"], cfg["orders"], int(cfg["T"])
@@ -204,9 +221,51 @@ def cpu_baseline(cfg, g, seed, target_s=15.0):
     dt = time.perf_counter() - t2
     del U, C, U1
     return {"value": count / dt, "unit": "edge samples/s", "cores": threads, "kind": "oracle",
+            "affinity_cores": cores, "thread_cap": cap or None,
             "sample": f"samples [{probe}, {probe + count}) of the same workload and seed "
                       f"({count} samples, {dt:.1f} s), binary32 lock-free mode of the oracle, "
-                      f"{threads} OpenMP threads; alias build and init excluded"}
+                      f"{threads} OpenMP threads of {cores} in the affinity mask; alias build and init "
+                      "excluded"}
+
+
+def c3_embedding_error(cfg, g, seed, count=1 << 20, batch=65536):
+    """||X - X64||_F / ||X64||_F per table after the first `count` samples in SNAPSHOT mode
+    (batch B): bfloat16 tables and binary32 tables on the GPU against the oracle's binary64
+    SNAPSHOT run, with the floor of rounding X64 to nearest bfloat16."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2604_09419_amd import LH_TABLE_C, LH_TABLE_U, LH_TABLE_U1, Trainer
+    t0 = time.time()
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+    m = oracle.Model(tb, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], T=int(cfg["T"]), seed=seed,
+                     eta0=cfg["eta0"])
+    m.train(0, count, "snapshot", batch)
+    log(f"[bench] oracle SNAPSHOT of {count} samples in {time.time() - t0:.1f}s")
+    refs = {"U": (LH_TABLE_U, m.U), "C": (LH_TABLE_C, m.C), "U1": (LH_TABLE_U1, m.U1)}
+    out = {"samples": count, "batch": batch, "mode": "snapshot"}
+
+    def fro(x, ref):
+        return float(np.linalg.norm(x.astype(np.float64) - ref) / np.linalg.norm(ref))
+
+    for dtype in ("bf16", "fp32"):
+        tr = Trainer(g.n, g.src, g.dst, g.w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype=dtype,
+                     eta0=cfg["eta0"], seed=seed, total_samples=int(cfg["T"]), mode="snapshot", batch=batch)
+        tr.train_steps(0, count)
+        tr.check()
+        out[dtype] = {k: fro(tr.read(t).cpu().numpy(), ref) for k, (t, ref) in refs.items() if ref is not None}
+        tr.close()
+        del tr
+        torch.cuda.empty_cache()
+    out["nearest_bf16_floor"] = {
+        k: fro(torch.tensor(ref, dtype=torch.float32).to(torch.bfloat16).float().numpy(), ref)
+        for k, (_, ref) in refs.items() if ref is not None}
+    return out
+
+
+def _lib_batch_config(bt):
+    from paper_2604_09419_amd import _lib
+    return _lib.lh_batch_config(bt.b)
 
 
 def bench_batched(args):
@@ -230,7 +289,10 @@ def bench_batched(args):
     total_T = sum(sp["T"] for sp in specs)
     algo_bytes = sum(sp["T"] * algorithmic_bytes_per_sample(sp["d"], 5, 2, 2) for sp in specs)
     bt = BatchTrainer(trainers)
-    # (the library refuses zero-step timing runs of bfloat16 batches for now: default tiling)
+    t0 = time.time()
+    bt.tune(cache_path=args.tune_cache)
+    tuning = _lib_batch_config(bt)
+    log(f"[bench] C4 tiling {tuning} ({time.time() - t0:.1f}s)")
     bt.capture()
     times = []
     for i in range(args.warmup + args.steps):
@@ -247,17 +309,17 @@ def bench_batched(args):
         tr.init_embeddings()
         tr.train_steps(0, tr.T)
         seq_ms += tr.last_train_ms()
-    ms = sum(times) / len(times)
+    ms = median(times)
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     return {
-        "metric": "edge samples/sec, 64 graphs in one persistent hipGraph launch (bf16)",
+        "metric": "edge samples/sec, 64 graphs in one persistent hipGraph launch (bf16 tables)",
         "value": total_T / (ms * 1e-3), "unit": "edge samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32", "table_dtype": "bf16", "data": "synthetic",
         "config": {"workload": "C4: 64 directed R-MAT graphs, n log-uniform 1e3..2e6, mean degree 8..32, "
                                "lognormal weights, d in {64,128}, K=5, second order, bf16 tables, T_g = 20 m_g",
                    "graphs": len(specs), "total_samples": total_T, "sum_m": sum(sp["m"] for sp in specs),
-                   "hot_shadow": args.hot_shadow},
+                   "hot_shadow": args.hot_shadow, "tiling": tuning, "tiling_from": "lh_batch_tune"},
         "sequential_launches": {"ms": seq_ms, "samples_per_s": total_T / (seq_ms * 1e-3),
                                 "batched_speedup": seq_ms / ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -300,7 +362,8 @@ def bench_large(args):
     return {
         "metric": f"edge samples/sec at d=128,K=5 ({name}, bf16)", "value": T / (ms * 1e-3),
         "unit": "edge samples/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "table_dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"{name}: {graph}, 67108864 nodes, 2^30 arcs, d=128, K=5, second order, "
                                "bf16 tables", "T": T,
                    "kernel_config": tr.kernel_config(), "alias_build_s": build_s, "hot_shadow": args.hot_shadow},
@@ -313,13 +376,14 @@ def bench_large(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5", "C5U"])
     ap.add_argument("--c5-samples", type=float, default=None, help="override T for C5 and C5U")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
     ap.add_argument("--hot-shadow", action="store_true",
                     help="bfloat16 runs: hot rows accumulate in a binary32 shadow per launch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
@@ -360,8 +424,8 @@ def main():
     seed = cfg["seed"]
     tr, step_ms, kern_ms = run_gpu_leg(cfg, g, "fp32", args.steps, args.warmup, seed, args.tune_cache)
     T = int(cfg["T"])
-    ms_step = sum(step_ms) / len(step_ms)
-    ms_kern = sum(kern_ms) / len(kern_ms)
+    ms_step = median(step_ms)
+    ms_kern = median(kern_ms)
     bps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 4)
     achieved = bps * T / (ms_kern * 1e-3) / 1e9
     traffic = measured_traffic(TRAFFIC_PROFILE, tr.kernel_config(), T)
@@ -406,14 +470,15 @@ def main():
     if not args.no_bf16:
         tb, bsteps, bkern = run_gpu_leg(cfg, g, "bf16", max(1, args.steps), 1, seed, args.tune_cache,
                                         hot_shadow=args.hot_shadow)
-        bms = sum(bkern) / len(bkern)
+        bms = median(bkern)
+        bstep = median(bsteps)
         bbps = algorithmic_bytes_per_sample(cfg["d"], cfg["K"], cfg["orders"], 2)
         bach = bbps * T / (bms * 1e-3) / 1e9
         result["bf16"] = {
-            "samples_per_s": T / (sum(bsteps) / len(bsteps) * 1e-3),
+            "samples_per_s": T / (bstep * 1e-3),
             "train_only_samples_per_s": T / (bms * 1e-3),
             "speedup_train_vs_fp32": ms_kern / bms,
-            "speedup_step_vs_fp32": ms_step / (sum(bsteps) / len(bsteps)),
+            "speedup_step_vs_fp32": ms_step / bstep,
             "kernel_config": tb.kernel_config(),
             "hot_shadow": args.hot_shadow,
             "roofline": {"bound": "hbm", "achieved": bach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -429,8 +494,17 @@ def main():
     gold_path = os.path.join(GOLDEN, "c2_oracle_auc.json")
     if os.path.exists(gold_path):
         gold = json.load(open(gold_path))
-        result["auc_oracle_binary64"] = {k[4:]: v for k, v in gold.items()
-                                         if k.startswith("auc_") and not k.startswith("auc_init")}
+        ref = {k[4:]: v for k, v in gold.items() if k.startswith("auc_") and not k.startswith("auc_init")}
+        result["auc_oracle_binary64"] = ref
+        # every score within 0.005 of the oracle's, for each dtype that was measured
+        for key, got in (("fp32", result.get("auc_fp32")), ("bf16", result.get("bf16", {}).get("auc"))):
+            if got:
+                result.setdefault("auc_within_0.005_of_oracle", {})[key] = all(
+                    abs(v - ref[k]) <= 0.005 for k, v in got.items())
+
+    if not args.no_c3_error and not args.no_bf16:
+        result["c3_embedding_error"] = c3_embedding_error(cfg, g, seed)
+        log(f"[bench] C3 embedding error {result['c3_embedding_error']}")
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, g, seed)

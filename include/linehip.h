@@ -103,66 +103,95 @@ typedef struct {
 typedef struct lh_handle lh_handle;
 typedef struct lh_batch lh_batch;
 
-/* Create a handle for device `device` after validating *p.  Returns LH_ERR_NO_DEVICE
- * when no HIP device exists (so it can be probed without a GPU). */
+/* Create a handle for device `device` after validating *p (the inputs of Algorithm 1:
+ * d, K, lambda, eta, alpha_neg; Sec. V-A gives eta = 0.025).  Returns LH_ERR_NO_DEVICE
+ * when no HIP device exists (so it can be probed without a GPU).  *h is owned by the
+ * caller until lh_destroy. */
 LH_API lh_status lh_create(lh_handle **h, const lh_params *p, int device);
 
-/* Bytes of device memory the caller must provide for a graph with n nodes and m arcs:
- * *persist for lh_bind (alias tables, flags, SNAPSHOT buffers) and *scratch for
- * lh_build_alias (binary64 build arrays, free after that call's work has run).
- * Host-only; needs no device. */
+/* Bytes of device memory the caller must provide for a graph with n nodes and m arcs
+ * (the graph G = (V, E) of Algorithm 1's input): *persist for lh_bind (alias tables,
+ * flags, SNAPSHOT buffers of the Eq. (4) batch) and *scratch for lh_build_alias (binary64
+ * build arrays, free after that call's work has run).  Host-only; needs no device.
+ * LH_ERR_INVALID_ARG for n < 1, n or m >= 2^31, or SNAPSHOT with 3 n >= 2^32. */
 LH_API lh_status lh_workspace_size(const lh_params *p, int64_t n, int64_t m, size_t *persist,
                             size_t *scratch);
 
-/* Attach caller memory.  workspace: device, >= *persist bytes from lh_workspace_size
- * for the n and m later given to lh_set_graph, 256-byte aligned.  tables[3]: device
- * pointers to U, C, U1 ([n x d] each, lh_params.dtype), NULL for a table the orders
- * do not use.  stream: the hipStream_t every later call enqueues on. */
+/* Attach caller memory: the embedding tables U and C that Algorithm 1 outputs (and U1
+ * for first-order proximity).  workspace: device, >= *persist bytes from
+ * lh_workspace_size for the n and m later given to lh_set_graph, 256-byte aligned.
+ * tables[3]: device pointers to U, C, U1 ([n x d] each, lh_params.dtype, 16-byte
+ * aligned), NULL for a table the orders do not use.  stream: the hipStream_t every later
+ * call enqueues on.  The caller keeps ownership and must keep them alive while the handle
+ * uses them.  LH_ERR_INVALID_ARG for a NULL or misaligned pointer. */
 LH_API lh_status lh_bind(lh_handle *h, void *workspace, size_t bytes, void *const tables[3],
                   void *stream);
 
-/* The graph: n nodes, m arcs (src[a] -> dst[a], weight w[a]); device arrays that must
- * stay valid until lh_build_alias has returned.  An undirected edge is two arcs.  The
+/* The graph G = (V, E) of Algorithm 1's input: n nodes, m arcs (src[a] -> dst[a],
+ * weight w[a]); device arrays that must stay valid until lh_build_alias has returned.
+ * An undirected edge is two arcs.  The
  * endpoints and weights are checked by a kernel and the call synchronises the stream:
  * LH_ERR_OUT_OF_RANGE for an endpoint outside [0, n), LH_ERR_ZERO_WEIGHT for a negative,
  * NaN or infinite weight; the handle then has no graph. */
 LH_API lh_status lh_set_graph(lh_handle *h, int64_t n, int64_t m, const int32_t *src,
                        const int32_t *dst, const float *w);
 
-/* Build the edge alias table over the m arcs (weights w) and the negative alias table
- * over the n nodes (weights out-degree^0.75, Eq. (1)) with the binary64 canonical
- * chunked scan, and the per-node touch rates the Hogwild write path is chosen by.
+/* Build the edge alias table over the m arcs (weights w: the root-edge distribution of
+ * Algorithm 3) and the negative alias table over the n nodes (weights out-degree^0.75,
+ * Eq. (1)) with the binary64 canonical chunked scan, and the per-node touch rates the Hogwild write path is chosen by.
  * scratch: device, >= *scratch bytes from lh_workspace_size, free once the call has
  * returned (it synchronises the stream).  LH_ERR_ZERO_WEIGHT when the arcs' total weight
  * is zero (or m == 0). */
 LH_API lh_status lh_build_alias(lh_handle *h, void *scratch, size_t scratch_bytes);
 
-/* Replace (import) or copy out (export) one alias table: which = LH_ALIAS_EDGE (N = m)
- * or LH_ALIAS_NEG (N = n); thr uint64[N], alias int32[N], both device.  Import
- * validates nothing beyond sizes; export synchronises the stream. */
+/* Replace (import) or copy out (export) one alias table, the encoding of the edge
+ * distribution of Algorithm 3 (which = LH_ALIAS_EDGE, N = m) or of the negative
+ * distribution of Eq. (1) (LH_ALIAS_NEG, N = n): column c keeps itself when a draw's
+ * threshold word is below thr[c], else it yields alias[c].  thr uint64[N], alias int32[N],
+ * both device, caller-owned.  Import checks the entries on the device (an alias outside
+ * [0, N) is replaced by the column and reported by lh_check) and marks every row hot;
+ * export synchronises the stream.  LH_ERR_NOT_BUILT when the table does not exist yet. */
 LH_API lh_status lh_import_alias(lh_handle *h, int which, const uint64_t *thr, const int32_t *alias);
 LH_API lh_status lh_export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias);
 
-/* Fill the bound tables with the initial values: uniform on [-0.5/d, 0.5/d), element
- * (t, r, c) from Philox4x64-10 word c % 4 of key (seed, 2^32 | graph_id), counter
- * (r, c / 4, t, 0); bfloat16 tables take the round-to-nearest-even of that value. */
+/* Fill the bound tables with the initial values ("Initialize U and C" of Algorithm 1;
+ * the paper gives no distribution, here both tables are uniform on [-0.5/d, 0.5/d)):
+ * element (t, r, c) from Philox4x64-10 word c % 4 of key (seed, 2^32 | graph_id), counter
+ * (r, c / 4, t, 0), value ((x >> 40) - 2^23) 2^-24 / d; bfloat16 tables take the
+ * round-to-nearest-even of that value.  Enqueued; LH_ERR_NOT_BUILT before lh_set_graph. */
 LH_API lh_status lh_init_embeddings(lh_handle *h);
 
-/* Parity hook: the tuples of samples [first, first + count): u[i], v[i] (int32, device,
- * count each) and neg[i * K + k] (int32, device, count * K).  Sample s slot j uses
- * Philox4x64-10 key (seed, graph_id), counter (s, j, 0, 0). */
+/* The tuples of samples [first, first + count), as training draws them: the positive
+ * pair (u, v) is an arc drawn proportionally to its weight (Algorithm 3, root-edge
+ * selection) and the K negatives v- are drawn i.i.d. from q(v) ~ out-degree^0.75 (Eq. (1);
+ * Algorithm 1 draws them without rejection).  Sample s slot j (0 = the arc, 1..K the
+ * negatives) uses Philox4x64-10 key (seed, graph_id), counter (s, j, 0, 0).
+ * Outputs (device, caller-owned): u[i], v[i] (int32, count each) and neg[i * K + k]
+ * (int32, count * K; may be NULL when K = 0).  Enqueued, deterministic.
+ * LH_ERR_NOT_BUILT before both alias tables exist; LH_ERR_INVALID_ARG for a NULL output,
+ * a range that wraps past 2^64, or count >= 2^40. */
 LH_API lh_status lh_sample(lh_handle *h, uint64_t first, uint64_t count, int32_t *u, int32_t *v,
                     int32_t *neg);
 
-/* Train samples [first, first + count) in lh_params.mode.  Needs first + count <= T.
- * SNAPSHOT needs first % batch == 0 and processes batches [bB, min((b+1)B, end)). */
+/* Train samples [first, first + count) in lh_params.mode (Algorithm 1, local updates):
+ * per sample and order, x_j = A[u] . B[b_j] for the positive (j = 0) and the K negatives,
+ * g_0 = eta_s (1 - sigma(x_0)), g_k = -eta_s alpha_neg sigma(x_k), then LineUpdate /
+ * Eqs. (2)-(3): A[u] += sum_j (g_j B[b_j] - eta_s lambda A[u]) and
+ * B[b_j] += g_j A[u] - eta_s lambda B[b_j], all from the rows as they were before the
+ * sample; second order (A, B) = (U, C), first order A = B = U1, both on the same tuple.
+ * eta_s = eta0 (1 - s / T).  HOGWILD applies samples concurrently without locks;
+ * SNAPSHOT takes every increment of batch [bB, min((b+1)B, end)) against the tables at
+ * the batch start and adds each row's ordered sum once (Eq. (4)), bit-reproducibly.
+ * Enqueued.  LH_ERR_INVALID_ARG when first + count > T or (SNAPSHOT) first % batch != 0;
+ * LH_ERR_NOT_BUILT before both alias tables exist. */
 LH_API lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count);
 
-/* Pick the Hogwild kernel configuration (lanes per sample, 4-byte units per lane,
- * workgroups per compute unit) for this handle's shape by timing each candidate on
- * samples [0, probe) with the step size scaled to zero, so the tables are left as they
- * were.  cache_path (may be NULL) names a JSON file of earlier choices keyed by device,
- * dtype, d, K and orders; a hit skips the timing.  Synchronises. */
+/* (Execution only: the paper defines no tiling.)  Pick the Hogwild kernel
+ * configuration (lanes per sample, 4-byte units per lane, workgroups per compute unit)
+ * for this handle's shape by timing each candidate on samples [0, probe) with the step
+ * size scaled to zero, so the tables are left as they were (binary32 and bfloat16).
+ * cache_path (may be NULL) names a JSON file of earlier choices keyed by device, dtype,
+ * d, K and orders; a hit skips the timing.  Synchronises. */
 LH_API lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_path);
 
 /* The Hogwild kernel configuration in use: out[0] lanes per sample, out[1] 4-byte units
@@ -180,18 +209,22 @@ LH_API lh_status lh_kernel_config(const lh_handle *h, int32_t out[3]);
  * 1 <= workgroups <= 64; else LH_ERR_INVALID_ARG and the configuration is unchanged. */
 LH_API lh_status lh_set_kernel_config(lh_handle *h, const int32_t cfg[3]);
 
-/* Copy rows [row0, row0 + rows) of table t (LH_TABLE_*) to / from a binary32 device
- * buffer [rows x d]; bfloat16 tables convert (reads exactly, writes round to nearest even). */
+/* The output embeddings U and C of Algorithm 1 (and U1): copy rows [row0, row0 + rows)
+ * of table t (LH_TABLE_*) to / from a binary32 device buffer [rows x d] (caller-owned);
+ * bfloat16 tables convert (reads exactly, writes round to nearest even).  Enqueued.
+ * LH_ERR_INVALID_ARG for a table the orders do not use or rows outside [0, n). */
 LH_API lh_status lh_read_embeddings(lh_handle *h, int table, int64_t row0, int64_t rows, float *out);
 LH_API lh_status lh_write_embeddings(lh_handle *h, int table, int64_t row0, int64_t rows,
                               const float *in);
 
-/* Synchronise the stream and report device-side data errors (LH_ERR_OUT_OF_RANGE,
- * LH_ERR_ZERO_WEIGHT) recorded since the last lh_check, clearing them. */
+/* (Error reporting, no counterpart in the paper.)  Synchronise the stream and report
+ * device-side data errors (LH_ERR_OUT_OF_RANGE, LH_ERR_ZERO_WEIGHT) recorded since the
+ * last lh_check, clearing them. */
 LH_API lh_status lh_check(lh_handle *h);
 
-/* Kernel time of the last lh_train_steps call, in milliseconds, measured with HIP
- * events on the handle's stream (synchronises).  Returns 0 when nothing was timed. */
+/* (Measurement only.)  Kernel time of the last lh_train_steps call, in milliseconds,
+ * measured with HIP events on the handle's stream (synchronises).  Returns 0 when
+ * nothing was timed. */
 LH_API lh_status lh_last_train_ms(lh_handle *h, double *ms);
 
 LH_API const char *lh_status_string(lh_status s);
@@ -199,11 +232,17 @@ LH_API const char *lh_last_error(const lh_handle *h);
 LH_API lh_status lh_destroy(lh_handle *h);
 
 /* ---------------- Batched: many graphs in one persistent launch ----------------
+ * (An execution extension: each graph is trained exactly as lh_train_steps trains it,
+ * Algorithm 1 in HOGWILD mode; the paper trains one graph at a time.)
  * G handles (HOGWILD, second order, created and bound as above, alias tables built,
  * tables initialised) are trained together: one persistent kernel pulls (graph, chunk of
  * samples) items from a device work queue until every graph's [0, T_g) is done.
- * lh_batch_capture records the queue reset and the kernel into a hipGraph on the first
- * handle's stream; lh_batch_launch replays it.  lh_batch_tune times the kernel variants
+ * lh_batch_capture records the queue reset and the kernel into a hipGraph (captured on
+ * the first handle's stream); lh_batch_launch replays it on `stream` (a hipStream_t as
+ * void*, NULL = the first handle's stream), and lh_batch_run enqueues the same work
+ * without a graph.  When `stream` is another stream, the launch waits for the work
+ * already queued on the first handle's stream, and that stream waits for the launch, so
+ * the handles' later calls see its result.  lh_batch_tune times the kernel variants
  * (lanes per sample, samples per item, grid size) on this batch and keeps the fastest;
  * cache_path (may be NULL) names a JSON file of earlier choices keyed by device and shape.
  * The batch object owns two small device buffers (the graph descriptors and the work
@@ -212,9 +251,14 @@ LH_API lh_status lh_destroy(lh_handle *h);
 LH_API lh_status lh_batch_create(lh_batch **b, int G, lh_handle *const *graphs);
 LH_API lh_status lh_batch_tune(lh_batch *b, const char *cache_path);
 LH_API lh_status lh_batch_capture(lh_batch *b);
-LH_API lh_status lh_batch_launch(lh_batch *b);
-LH_API lh_status lh_batch_run(lh_batch *b);   /* same work as launch, without a graph */
+LH_API lh_status lh_batch_launch(lh_batch *b, void *stream);
+LH_API lh_status lh_batch_run(lh_batch *b, void *stream);   /* same work as launch, without a graph */
 LH_API lh_status lh_batch_last_ms(lh_batch *b, double *ms);
+/* The batch's kernel configuration (host memory, 3 int64): out[0] the tile variant (0: one
+ * 4-byte unit per lane for bfloat16 / four for binary32; 1: four / eight), out[1]
+ * workgroups per compute unit, out[2] samples per work item; set by lh_batch_tune or the
+ * defaults. */
+LH_API lh_status lh_batch_config(const lh_batch *b, int64_t out[3]);
 /* Samples trained per graph by the last launch/run (uint64[G], host; synchronises). */
 LH_API lh_status lh_batch_done(lh_batch *b, uint64_t *done_per_graph);
 LH_API lh_status lh_batch_destroy(lh_batch *b);

@@ -195,11 +195,13 @@ class BatchTrainer:
     def capture(self):
         _lib.lh_batch_capture(self.b)
 
-    def launch(self):
-        _lib.lh_batch_launch(self.b)
+    def launch(self, stream=None):
+        """Replay the captured launch on ``stream`` (a torch stream; None: the trainers'
+        stream)."""
+        _lib.lh_batch_launch(self.b, stream.cuda_stream if stream is not None else 0)
 
-    def run(self):
-        _lib.lh_batch_run(self.b)
+    def run(self, stream=None):
+        _lib.lh_batch_run(self.b, stream.cuda_stream if stream is not None else 0)
 
     def last_ms(self) -> float:
         return _lib.lh_batch_last_ms(self.b)

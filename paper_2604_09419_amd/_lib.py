@@ -88,9 +88,10 @@ def lib() -> ctypes.CDLL:
         "lh_batch_create": [PP, S, ctypes.POINTER(ctypes.c_void_p)],
         "lh_batch_tune": [P, ctypes.c_char_p],
         "lh_batch_capture": [P],
-        "lh_batch_launch": [P],
-        "lh_batch_run": [P],
+        "lh_batch_launch": [P, P],
+        "lh_batch_run": [P, P],
         "lh_batch_last_ms": [P, ctypes.POINTER(ctypes.c_double)],
+        "lh_batch_config": [P, ctypes.POINTER(ctypes.c_int64 * 3)],
         "lh_batch_done": [P, P],
         "lh_batch_destroy": [P],
     }
@@ -225,18 +226,24 @@ def lh_batch_capture(b):
     check(lib().lh_batch_capture(b), "lh_batch_capture")
 
 
-def lh_batch_launch(b):
-    check(lib().lh_batch_launch(b), "lh_batch_launch")
+def lh_batch_launch(b, stream: int = 0):
+    check(lib().lh_batch_launch(b, stream or None), "lh_batch_launch")
 
 
-def lh_batch_run(b):
-    check(lib().lh_batch_run(b), "lh_batch_run")
+def lh_batch_run(b, stream: int = 0):
+    check(lib().lh_batch_run(b, stream or None), "lh_batch_run")
 
 
 def lh_batch_last_ms(b) -> float:
     ms = ctypes.c_double()
     check(lib().lh_batch_last_ms(b, ctypes.byref(ms)), "lh_batch_last_ms")
     return ms.value
+
+
+def lh_batch_config(b):
+    out = (ctypes.c_int64 * 3)()
+    check(lib().lh_batch_config(b, ctypes.byref(out)), "lh_batch_config")
+    return {"variant": out[0], "blocks_per_cu": out[1], "item_samples": out[2]}
 
 
 def lh_batch_done(b, G: int):

@@ -118,7 +118,7 @@ static const char *const kSymbols[] = {
     "lh_import_alias",    "lh_export_alias",   "lh_init_embeddings", "lh_sample",        "lh_train_steps",
     "lh_read_embeddings", "lh_write_embeddings", "lh_check",       "lh_last_train_ms",   "lh_tune",   "lh_kernel_config", "lh_set_kernel_config",
     "lh_status_string",   "lh_last_error",     "lh_destroy",       "lh_batch_create",    "lh_batch_tune",
-    "lh_batch_capture",   "lh_batch_launch",   "lh_batch_run",     "lh_batch_last_ms",   "lh_batch_done",      "lh_batch_destroy",
+    "lh_batch_capture",   "lh_batch_launch",   "lh_batch_run",     "lh_batch_last_ms",   "lh_batch_config",    "lh_batch_done",      "lh_batch_destroy",
     "lh_abi_symbol_count", "lh_abi_symbol_name",
 };
 

@@ -96,9 +96,6 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     if (!h->bound || !h->graph_set || !h->edge_ready || !h->neg_ready)
         return fail(h, LH_ERR_NOT_BUILT, "alias tables not built");
     if (h->p.mode != LH_HOGWILD) return LH_OK;
-    // Timing runs of bfloat16 tables are switched off: a zero-step timing run of the
-    // bfloat16 kernel did not finish on the GPU and its cause is not yet known.
-    if (h->p.dtype == LH_BF16) return fail(h, LH_ERR_UNSUPPORTED, "tuning bfloat16 tables is switched off");
     if (probe < 64 || probe > h->p.total_samples) return fail(h, LH_ERR_INVALID_ARG, "probe out of range");
     int dev = -1;
     (void)hipGetDevice(&dev);
@@ -120,36 +117,49 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     }
     const int nu = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;
     GraphDev g = graph_dev(h);
-    g.eta_scale = 0.0f;  // dry run: every row is written back unchanged
-    const int lps_opts[] = {2, 4, 8, 16, 32, 64};
+    // Dry run: the step size is scaled to zero, so every row is written back unchanged,
+    // and hot rows still issue their atomics (bfloat16 ones too, whose zero increments a
+    // training run skips), so the timing includes what the hot set costs.
+    g.eta_scale = 0.0f;
     const int bpc_opts[] = {1, 2, 3, 4, 8, 16};
+    // Candidate shapes: the compiled (lanes, units) that cover a row with the fewest
+    // 4-byte slots (wider groups would only idle lanes).
+    std::vector<TileCfg> shapes;
+    int cover = 1 << 30;
+#define LH_TUNE_COVER(L, U) \
+    if (L * U >= nu && L * U < cover) cover = L * U;
+    LH_CFG_LIST(LH_TUNE_COVER)
+#undef LH_TUNE_COVER
+#define LH_TUNE_SHAPE(L, U)      \
+    if (L * U == cover) {        \
+        TileCfg c;               \
+        c.lps = L;               \
+        c.upl = U;               \
+        shapes.push_back(c);     \
+    }
+    LH_CFG_LIST(LH_TUNE_SHAPE)
+#undef LH_TUNE_SHAPE
     TileCfg best = h->cfg;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LH_ERR_HIP;
-    for (int upl : {2, 4, 8}) {
-        for (int lps : lps_opts) {
-            TileCfg c;
-            c.lps = lps;
-            c.upl = upl;
-            if (lps * upl < nu || (lps * upl >= 2 * nu && lps > 2)) continue;
-            for (int bpc : bpc_opts) {
-                c.blocks_per_cu = bpc;
-                if (!cfg_supported(h->p.dtype, h->p.d, c)) continue;
-                // warm-up, then timed
-                hipError_t er = launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe / 4, h->num_cu, nullptr,
-                                               h->stream);
-                if (er != hipSuccess) continue;
-                (void)hipEventRecord(e0, h->stream);
-                (void)launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe, h->num_cu, nullptr, h->stream);
-                (void)hipEventRecord(e1, h->stream);
-                if (hipEventSynchronize(e1) != hipSuccess) continue;
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
-                }
+    for (TileCfg c : shapes) {
+        for (int bpc : bpc_opts) {
+            c.blocks_per_cu = bpc;
+            if (!cfg_supported(h->p.dtype, h->p.d, c)) continue;
+            // warm-up, then timed
+            hipError_t er = launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe / 4, h->num_cu, nullptr,
+                                           h->stream);
+            if (er != hipSuccess) continue;
+            (void)hipEventRecord(e0, h->stream);
+            (void)launch_hogwild(g, h->p.dtype, h->p.orders, c, 0, probe, h->num_cu, nullptr, h->stream);
+            (void)hipEventRecord(e1, h->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
             }
         }
     }
@@ -278,6 +288,7 @@ struct lh_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t join0 = nullptr, join1 = nullptr;  // ordering against a caller's stream
     bool timed = false;
 };
 
@@ -367,7 +378,8 @@ static void batch_items(lh_batch *b, unsigned long long item_samples, bool dry, 
     b->total_items = acc;
 }
 
-static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned long long item_samples)
+static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned long long item_samples,
+                                   hipStream_t s)
 {
     BatchArgs a;
     a.desc = b->d_desc;
@@ -377,7 +389,6 @@ static hipError_t batch_launch_raw(lh_batch *b, int variant, int bpc, unsigned l
     a.item_samples = item_samples;
     a.queue = b->d_ctr;
     a.done = b->d_ctr + 1;
-    hipStream_t s = b->stream;
     // bfloat16 graphs with a shadow: their hot rows move into it for the launch.
     for (int i = 0; i < b->G; ++i) {
         ShadowCtx sc;
@@ -423,6 +434,27 @@ static hipError_t upload_desc(lh_batch *b)
     if (e == hipSuccess && !b->sched.empty())
         e = hipMemcpyAsync(b->d_sched, b->sched.data(), sizeof(unsigned long long) * b->sched.size(),
                            hipMemcpyHostToDevice, b->stream);
+    return e;
+}
+
+// The stream a launch or run goes on (NULL: the first handle's stream).  Another stream
+// first waits for the work queued on the handles' stream.
+static hipStream_t enter_stream(lh_batch *b, void *stream)
+{
+    hipStream_t s = stream ? (hipStream_t)stream : b->stream;
+    if (s != b->stream) {
+        (void)hipEventRecord(b->join0, b->stream);
+        (void)hipStreamWaitEvent(s, b->join0, 0);
+    }
+    return s;
+}
+
+// After the launch: the handles' stream waits for it, so their later calls see its result.
+static hipError_t leave_stream(lh_batch *b, hipStream_t s)
+{
+    if (s == b->stream) return hipSuccess;
+    hipError_t e = hipEventRecord(b->join1, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->join1, 0);
     return e;
 }
 
@@ -474,7 +506,9 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
     if (hipMalloc(&b->d_desc, sizeof(BatchDesc) * G) != hipSuccess ||
         hipMalloc(&b->d_sched, sizeof(unsigned long long) * (b->sched_cap + 1)) != hipSuccess ||
         hipMalloc(&b->d_ctr, sizeof(unsigned long long) * (G + 1)) != hipSuccess ||
-        hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+        hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join0, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join1, hipEventDisableTiming) != hipSuccess) {
         lh_batch_destroy(b);
         return LH_ERR_HIP;
     }
@@ -490,8 +524,6 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
 lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
 {
     if (!b) return LH_ERR_INVALID_ARG;
-    // Same restriction as lh_tune: no zero-step timing runs of bfloat16 kernels for now.
-    if (b->dtype == LH_BF16) return LH_ERR_UNSUPPORTED;
     char key[160];
     unsigned long long tot = 0;
     for (auto *h : b->hs) tot += h->p.total_samples;
@@ -522,9 +554,9 @@ lh_status lh_batch_tune(lh_batch *b, const char *cache_path)
                 b->blocks_per_cu = bpc;
                 batch_items(b, is, true, probe);
                 if (upload_desc(b) != hipSuccess) return LH_ERR_HIP;
-                if (batch_launch_raw(b, v, bpc, is) != hipSuccess) return LH_ERR_HIP;  // warm-up
+                if (batch_launch_raw(b, v, bpc, is, b->stream) != hipSuccess) return LH_ERR_HIP;  // warm-up
                 (void)hipEventRecord(b->ev0, b->stream);
-                (void)batch_launch_raw(b, v, bpc, is);
+                (void)batch_launch_raw(b, v, bpc, is, b->stream);
                 (void)hipEventRecord(b->ev1, b->stream);
                 if (hipEventSynchronize(b->ev1) != hipSuccess) return LH_ERR_HIP;
                 float ms = 0;
@@ -554,7 +586,7 @@ lh_status lh_batch_capture(lh_batch *b)
     batch_items(b, b->item_samples, false, 0);
     if (upload_desc(b) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) return LH_ERR_HIP;
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LH_ERR_HIP;
-    hipError_t e = batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples);
+    hipError_t e = batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples, b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &b->graph);
     if (e != hipSuccess || e2 != hipSuccess) {
         drop_graph(b);
@@ -567,27 +599,29 @@ lh_status lh_batch_capture(lh_batch *b)
     return LH_OK;
 }
 
-lh_status lh_batch_launch(lh_batch *b)
+lh_status lh_batch_launch(lh_batch *b, void *stream)
 {
     if (!b) return LH_ERR_INVALID_ARG;
     if (!b->exec) return LH_ERR_NOT_BUILT;
-    (void)hipEventRecord(b->ev0, b->stream);
-    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return LH_ERR_HIP;
-    (void)hipEventRecord(b->ev1, b->stream);
+    hipStream_t s = enter_stream(b, stream);
+    (void)hipEventRecord(b->ev0, s);
+    if (hipGraphLaunch(b->exec, s) != hipSuccess) return LH_ERR_HIP;
+    (void)hipEventRecord(b->ev1, s);
     b->timed = true;
-    return LH_OK;
+    return leave_stream(b, s) == hipSuccess ? LH_OK : LH_ERR_HIP;
 }
 
-lh_status lh_batch_run(lh_batch *b)
+lh_status lh_batch_run(lh_batch *b, void *stream)
 {
     if (!b) return LH_ERR_INVALID_ARG;
     batch_items(b, b->item_samples, false, 0);
     if (upload_desc(b) != hipSuccess) return LH_ERR_HIP;
-    (void)hipEventRecord(b->ev0, b->stream);
-    if (batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples) != hipSuccess) return LH_ERR_HIP;
-    (void)hipEventRecord(b->ev1, b->stream);
+    hipStream_t s = enter_stream(b, stream);
+    (void)hipEventRecord(b->ev0, s);
+    if (batch_launch_raw(b, b->variant, b->blocks_per_cu, b->item_samples, s) != hipSuccess) return LH_ERR_HIP;
+    (void)hipEventRecord(b->ev1, s);
     b->timed = true;
-    return LH_OK;
+    return leave_stream(b, s) == hipSuccess ? LH_OK : LH_ERR_HIP;
 }
 
 lh_status lh_batch_last_ms(lh_batch *b, double *ms)
@@ -599,6 +633,15 @@ lh_status lh_batch_last_ms(lh_batch *b, double *ms)
     float f = 0;
     if (hipEventElapsedTime(&f, b->ev0, b->ev1) != hipSuccess) return LH_ERR_HIP;
     *ms = f;
+    return LH_OK;
+}
+
+lh_status lh_batch_config(const lh_batch *b, int64_t out[3])
+{
+    if (!b || !out) return LH_ERR_INVALID_ARG;
+    out[0] = b->variant;
+    out[1] = b->blocks_per_cu;
+    out[2] = (int64_t)b->item_samples;
     return LH_OK;
 }
 
@@ -622,6 +665,8 @@ lh_status lh_batch_destroy(lh_batch *b)
     if (b->d_ctr) (void)hipFree(b->d_ctr);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->join0) (void)hipEventDestroy(b->join0);
+    if (b->join1) (void)hipEventDestroy(b->join1);
     delete b;
     return LH_OK;
 }

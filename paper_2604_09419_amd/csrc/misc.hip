@@ -191,7 +191,8 @@ hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCf
 }
 
 // ---------------------------------------------------------------------------
-// Sampling: one thread per sample, the same draw as phase A of the training tile.
+// Sampling: one thread per sample, with the draw functions phase A of the training tile
+// uses (draw_slot, load_edge_rec, edge_pick, neg_pick).
 // ---------------------------------------------------------------------------
 __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long long count, int32_t *u, int32_t *v,
                          int32_t *neg)
@@ -199,17 +200,19 @@ __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long lon
     unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const unsigned long long s = first + i;
-    u64x4 x = philox4x64_10(g.seed, g.key1, s, 0ull, 0ull, 0ull);
-    long long ce = draw_column(x.x, g.m);
-    EdgeRec r = g.erec[ce];
-    bool keep = x.y < r.thr;
-    u[i] = keep ? r.src_c : r.src_a;
-    v[i] = keep ? r.dst_c : r.dst_a;
+    const SlotDraw de = draw_slot(g, s, 0, g.m);
+    uint4 r0, r1;
+    load_edge_rec(g.erec, de.col, r0, r1);
+    int uu = 0, vv = 0;
+    (void)edge_pick(r0, r1, de.x1, uu, vv);
+    u[i] = uu;
+    v[i] = vv;
     for (int j = 1; j <= g.K; ++j) {
-        u64x4 y = philox4x64_10(g.seed, g.key1, s, (unsigned long long)j, 0ull, 0ull);
-        long long cn = draw_column(y.x, g.n);
-        NegRec nr = g.nrec[cn];
-        neg[i * (unsigned long long)g.K + (j - 1)] = y.y < nr.thr ? (int32_t)cn : nr.alias;
+        const SlotDraw dn = draw_slot(g, s, j, g.n);
+        const uint4 nr = *reinterpret_cast<const uint4 *>(g.nrec + dn.col);
+        int id = 0;
+        (void)neg_pick(nr, dn, id);
+        neg[i * (unsigned long long)g.K + (j - 1)] = id;
     }
 }
 

@@ -66,6 +66,50 @@ __device__ __forceinline__ uint32_t f32_to_unit(const float (&x)[Elem<TT>::EPU],
     }
 }
 
+// ---- drawing one sample (shared by the parity hook k_sample and phase A) ------------
+// Slot j of sample s (0: the positive arc, Algorithm 3's root edge; 1..K: negatives of
+// Eq. (1), Algorithm 1) uses Philox4x64-10 block (key (seed, graph_id), counter
+// (s, j, 0, 0)): column floor(x0 N / 2^64), kept when x1 < thr[column], else its alias.
+struct SlotDraw {
+    long long col;             // column of the alias table
+    unsigned long long x1;     // threshold word
+    unsigned long long x2;     // a spare word of the block (seeds of the rounding bits)
+};
+
+__device__ __forceinline__ SlotDraw draw_slot(const GraphDev &g, unsigned long long s, int j, long long N)
+{
+    const u64x4 x = philox4x64_10(g.seed, g.key1, s, (unsigned long long)j, 0ull, 0ull);
+    return SlotDraw{draw_column(x.x, N), x.y, x.z};
+}
+
+// The 32-byte edge record of a column as two 16-byte words (one sector).
+__device__ __forceinline__ void load_edge_rec(const EdgeRec *erec, long long col, uint4 &r0, uint4 &r1)
+{
+    const uint4 *er = reinterpret_cast<const uint4 *>(erec + col);
+    r0 = er[0];
+    r1 = er[1];
+}
+
+// The arc (u, v) a slot-0 draw picks from its record words (threshold r0.xy, column arc's
+// endpoints r0.w, r1.x, alias arc's r1.y, r1.z); returns whether the column kept itself.
+__device__ __forceinline__ bool edge_pick(const uint4 &r0, const uint4 &r1, unsigned long long x1, int &u, int &v)
+{
+    const unsigned long long thr = (unsigned long long)r0.x | ((unsigned long long)r0.y << 32);
+    const bool keep = x1 < thr;
+    u = keep ? (int)r0.w : (int)r1.y;
+    v = keep ? (int)r1.x : (int)r1.z;
+    return keep;
+}
+
+// The node a negative draw picks from its 16-byte record (threshold nr.xy, alias nr.z).
+__device__ __forceinline__ bool neg_pick(const uint4 &nr, const SlotDraw &d, int &id)
+{
+    const unsigned long long thr = (unsigned long long)nr.x | ((unsigned long long)nr.y << 32);
+    const bool keep = d.x1 < thr;
+    id = keep ? (int)d.col : (int)nr.z;
+    return keep;
+}
+
 // Where SNAPSHOT contributions go.
 struct SnapOut {
     uint32_t *keys;           // [entries]  table * n + row
@@ -290,7 +334,9 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
                         const float nv = __uint_as_float(f32_to_bf16_sr(o + inc[k][e], rnd >> (16 * e)) << 16);
                         p |= f32_to_bf16_rne(nv - o) << (16 * e);
                     }
-                    if ((p & 0x7fff7fffu) != 0u)
+                    // (a dry run, step size scaled to zero, issues them all, so that a
+                    // timing run pays for the hot set as training does)
+                    if ((p & 0x7fff7fffu) != 0u || g.eta_scale == 0.0f)
                         __builtin_amdgcn_global_atomic_fadd_v2bf16(
                             (short2_t __attribute__((address_space(1))) *)(w + un),
                             __builtin_bit_cast(short2_t, p));
@@ -480,32 +526,24 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
             // One Philox block at a time, its record load issued at once, so the loads of
             // all 1 + K slots are in flight together while the blocks are not interleaved
             // (which would hold 1 + K blocks of state in registers).
-            u64x4 x0 = philox4x64_10(g.seed, g.key1, s, 0ull, 0ull, 0ull);
-            long long ce = draw_column(x0.x, g.m);
-            const uint4 *er = reinterpret_cast<const uint4 *>(g.erec + ce);
-            uint4 r0 = er[0], r1 = er[1];
-            const unsigned long long x0y = x0.y;
-            my_sr = (uint32_t)x0.z;
+            const SlotDraw de = draw_slot(g, s, 0, g.m);
+            uint4 r0, r1;
+            load_edge_rec(g.erec, de.col, r0, r1);
+            my_sr = (uint32_t)de.x2;
             __builtin_amdgcn_sched_barrier(0);
-            unsigned long long xy[KMAX];
-            int cn[KMAX];
+            SlotDraw dn[KMAX];
             uint4 nr[KMAX];
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 if (j < K) {
-                    u64x4 x = philox4x64_10(g.seed, g.key1, s, (unsigned long long)(j + 1), 0ull, 0ull);
-                    cn[j] = (int)draw_column(x.x, g.n);
-                    xy[j] = x.y;
-                    nr[j] = *reinterpret_cast<const uint4 *>(g.nrec + cn[j]);
+                    dn[j] = draw_slot(g, s, j + 1, g.n);
+                    nr[j] = *reinterpret_cast<const uint4 *>(g.nrec + dn[j].col);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
             my_eta = (float)(g.eta0 * (1.0 - (double)s / (double)g.T)) * g.eta_scale;
             const unsigned hh = (unsigned)g.hot_heat;  // -1 wraps to "nothing is that cold"
-            unsigned long long ethr = (unsigned long long)r0.x | ((unsigned long long)r0.y << 32);
-            bool keep = x0y < ethr;
-            my_u = keep ? (int)r0.w : (int)r1.y;
-            my_ids[0] = keep ? (int)r1.x : (int)r1.z;
+            const bool keep = edge_pick(r0, r1, de.x1, my_u, my_ids[0]);
             const unsigned eh = r1.w;  // heats: src_c, dst_c, src_a, dst_a
             const unsigned hu = keep ? (eh & 0xffu) : ((eh >> 16) & 0xffu);
             const unsigned hv = keep ? ((eh >> 8) & 0xffu) : (eh >> 24);
@@ -513,9 +551,7 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 if (j < K) {
-                    unsigned long long nthr = (unsigned long long)nr[j].x | ((unsigned long long)nr[j].y << 32);
-                    const bool kc = xy[j] < nthr;
-                    my_ids[j + 1] = kc ? cn[j] : (int)nr[j].z;
+                    const bool kc = neg_pick(nr[j], dn[j], my_ids[j + 1]);
                     const unsigned hn = kc ? (nr[j].w & 0xffu) : ((nr[j].w >> 8) & 0xffu);
                     if (g.hot_heat >= 0 && hn <= hh) my_hot |= 4u << j;
                 }

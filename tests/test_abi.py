@@ -97,7 +97,10 @@ def test_null_handles_rejected(L):
     assert L.lh_train_steps(None, 0, 1) == 1
     assert L.lh_check(None) == 1
     assert L.lh_destroy(None) == 1
-    assert L.lh_batch_launch(None) == 1
+    assert L.lh_batch_launch(None, None) == 1
+    assert L.lh_batch_run(None, None) == 1
+    out = (ctypes.c_int64 * 3)()
+    assert L.lh_batch_config(None, ctypes.byref(out)) == 1
     cfg = (ctypes.c_int32 * 3)(64, 2, 2)
     assert L.lh_set_kernel_config(None, ctypes.byref(cfg)) == 1
     assert L.lh_kernel_config(None, ctypes.byref(cfg)) == 1

@@ -107,14 +107,16 @@ def test_sampler_bit_exact(c1_graph, c1_tables, first, count):
     tr.import_alias(lh.LH_ALIAS_NEG, c1_tables.nthr.view(np.int64), c1_tables.nalias)
     tr.check()
     u2, v2, n2 = tr.sample(first, count)
-    assert np.array_equal(u2.cpu().numpy(), ou) and np.array_equal(n2.cpu().numpy(), oneg)
+    assert np.array_equal(u2.cpu().numpy(), ou) and np.array_equal(v2.cpu().numpy(), ov)
+    assert np.array_equal(n2.cpu().numpy(), oneg)
 
 
 def test_sampler_graph_ids_and_k(c1_graph, c1_tables):
     tr = trainer_for(c1_graph, d=16, K=3, seed=5, graph_id=9, total_samples=10, init=False)
     u, v, neg = tr.sample(123, 5000)
     ou, ov, oneg = oracle.sample(c1_tables, seed=5, graph_id=9, K=3, first=123, count=5000)
-    assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(neg.cpu().numpy(), oneg)
+    assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov)
+    assert np.array_equal(neg.cpu().numpy(), oneg)
 
 
 # ---------------------------------------------------------------------------
@@ -160,6 +162,55 @@ def test_snapshot_c1_within_1e5(c1_graph, c1_tables, B, count):
         err = max_row_rel_err(x, ref)
         print(f"snapshot C1 B={B} table {name}: max row rel err {err:.3e}", flush=True)
         assert err <= 1e-5, (name, err)
+
+
+@pytest.mark.parametrize("K,orders,lam,alpha", [(0, 3, 0.01, 1.0), (1, 2, 0.02, 0.5), (1, 1, 0.0, 2.0),
+                                                 (8, 3, 0.005, 0.75), (8, 1, 0.01, 1.5), (3, 2, 0.0, 1.0)])
+def test_snapshot_every_k_lambda_alpha_within_1e5(c1_graph, c1_tables, K, orders, lam, alpha):
+    """SNAPSHOT with weight decay, a negative weight other than 1 and K in {0, 1, 3, 8}
+    (K = 8 runs the kernels built for up to eight negatives), both orders: binary32 GPU vs
+    binary64 oracle per row within 1e-5."""
+    lh = _lh()
+    T, B, count = 400_000, 777, 200_000
+    tr = trainer_for(c1_graph, d=16, K=K, orders=orders, seed=8, total_samples=T, mode="snapshot", batch=B,
+                     lam=lam, alpha_neg=alpha, eta0=0.05)
+    tr.train_steps(0, count)
+    tr.check()
+    m = oracle.Model(c1_tables, d=16, K=K, orders=orders, T=T, seed=8, eta0=0.05, lam=lam, alpha=alpha)
+    m.train(0, count, "snapshot", B)
+    for name, tab, ref in (("U", lh.LH_TABLE_U, m.U), ("C", lh.LH_TABLE_C, m.C), ("U1", lh.LH_TABLE_U1, m.U1)):
+        if ref is None:
+            continue
+        err = max_row_rel_err(tr.read(tab).cpu().numpy(), ref)
+        print(f"snapshot K={K} orders={orders} lambda={lam} alpha={alpha} table {name}: {err:.3e}", flush=True)
+        assert err <= 1e-5, (name, err)
+
+
+@pytest.mark.parametrize("dtype,K,lam,alpha", [("fp32", 8, 0.001, 0.75), ("bf16", 8, 0.001, 0.75),
+                                               ("fp32", 1, 0.0, 1.5), ("bf16", 0, 0.002, 1.0)])
+def test_hogwild_c1_k_lambda_alpha_auc_matches_oracle(dtype, K, lam, alpha):
+    """Hogwild with K in {0, 1, 8}, weight decay and a negative weight other than 1 (the
+    Hogwild kernels built for up to eight negatives, and the K = 0 path), on C1 with 1 %
+    held out: held-out AUCs within 0.005 of the oracle's SEQ binary64 run of the same
+    samples (computed here)."""
+    lh = _lh()
+    g, hs, hd, neg = config_graph("C1", holdout=True)
+    T = 1_000_000
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    m = oracle.Model(t, d=16, K=K, orders=2, T=T, seed=3, lam=lam, alpha=alpha)
+    m.train(0, T, "seq")
+    ref_uc = oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2))
+    ref_uu = oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg))
+    tr = trainer_for(g, d=16, K=K, orders=2, dtype=dtype, seed=3, total_samples=T, lam=lam, alpha_neg=alpha)
+    tr.train_steps(0, T)
+    tr.check()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    uc = oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg))
+    uu = oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
+    print(f"C1 {dtype} K={K} lambda={lam} alpha={alpha}: uc {uc:.4f} (oracle {ref_uc:.4f}) "
+          f"uu {uu:.4f} (oracle {ref_uu:.4f})", flush=True)
+    assert abs(uc - ref_uc) <= 0.005 and abs(uu - ref_uu) <= 0.005
 
 
 def test_snapshot_orders12_ragged_batches(c1_graph, c1_tables):
@@ -237,36 +288,84 @@ def _held_out_aucs(tr, hs, hd, neg, orders):
     return out
 
 
+TUNE_CACHE = os.path.join(os.path.dirname(GOLDEN), "..", "paper_2604_09419_amd", "tune_cache.json")
+
+
+def _bench_shape(tr, T, tmp_path):
+    """The tile shape bench.py times: lh_tune with the committed tuning cache (a copy, so a
+    miss that tunes here leaves the committed file alone), probe min(T, 2e7)."""
+    import shutil
+    cache = str(tmp_path / "tune_cache.json")
+    if os.path.exists(TUNE_CACHE):
+        shutil.copy(TUNE_CACHE, cache)
+    tr.tune(probe=min(T, 20_000_000), cache_path=cache)
+    return tr.kernel_config()
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
-def test_hogwild_c2_auc_matches_oracle(dtype):
-    """C2 (and C3 for bfloat16) at full size, in the launch configuration bench.py times:
-    every held-out AUC within 0.005 of the binary64 oracle's SEQ run."""
+def test_hogwild_c2_auc_matches_oracle(dtype, tmp_path):
+    """C2 (and C3 for bfloat16) at full size, in the launch configuration bench.py times
+    (its tuning cache, its probe): every held-out AUC within 0.005 of the binary64
+    oracle's SEQ run."""
     gold = json.load(open(os.path.join(GOLDEN, "c2_oracle_auc.json")))
     g, hs, hd, neg = _c2()
     tr = trainer_for(g, d=128, K=5, orders=3, dtype=dtype, seed=gold["seed"], total_samples=gold["T"])
+    cfg = _bench_shape(tr, gold["T"], tmp_path)
     tr.train_steps(0, gold["T"])
     tr.check()
     got = _held_out_aucs(tr, hs, hd, neg, 3)
-    print(f"C2 {dtype} hogwild: " + " ".join(f"{k} {v:.4f} (oracle {gold['auc_' + k]:.4f})" for k, v in got.items()),
-          flush=True)
+    print(f"C2 {dtype} hogwild {cfg}: " + " ".join(f"{k} {v:.4f} (oracle {gold['auc_' + k]:.4f})"
+                                                  for k, v in got.items()), flush=True)
     for k, v in got.items():
         assert abs(v - gold["auc_" + k]) <= 0.005, (k, v, gold["auc_" + k])
 
 
-def test_snapshot_c2_prefix_within_1e5():
-    """The first 2^20 samples of C2 in SNAPSHOT mode (B = 65536), binary32 GPU vs binary64 oracle."""
-    lh = _lh()
-    g, _, _, _ = _c2()
-    t = oracle.Tables(g.n, g.src, g.dst, g.w)
-    count, B = 1 << 20, 65536
-    tr = trainer_for(g, d=128, K=5, orders=3, seed=2, total_samples=200_000_000, mode="snapshot", batch=B)
-    tr.train_steps(0, count)
+@pytest.mark.parametrize("dtype,shape", [("bf16", (64, 1, 16)), ("bf16", (32, 2, 16)), ("bf16", (16, 4, 8)),
+                                         ("fp32", (64, 2, 2)), ("fp32", (32, 4, 8))])
+def test_hogwild_c2_every_bench_shape_matches_oracle(dtype, shape):
+    """The tile shapes the one-graph bfloat16 and binary32 kernels run (one or two samples
+    per wavefront, the C5 shape (32, 2, 16) among them) on the full C2 graph: every held-out
+    AUC within 0.005 of the binary64 oracle."""
+    gold = json.load(open(os.path.join(GOLDEN, "c2_oracle_auc.json")))
+    g, hs, hd, neg = _c2()
+    tr = trainer_for(g, d=128, K=5, orders=3, dtype=dtype, seed=gold["seed"], total_samples=gold["T"])
+    tr.set_kernel_config(*shape)
+    tr.train_steps(0, gold["T"])
     tr.check()
-    m = oracle.Model(t, d=128, K=5, orders=3, T=200_000_000, seed=2)
-    m.train(0, count, "snapshot", B)
+    got = _held_out_aucs(tr, hs, hd, neg, 3)
+    print(f"C2 {dtype} {shape}: " + " ".join(f"{k} {v:.4f} (oracle {gold['auc_' + k]:.4f})"
+                                            for k, v in got.items()), flush=True)
+    for k, v in got.items():
+        assert abs(v - gold["auc_" + k]) <= 0.005, (k, v, gold["auc_" + k])
+
+
+_PREFIX = {}
+
+
+@pytest.mark.parametrize("part", [0, 1, 2, 3])
+def test_snapshot_c2_prefix_within_1e5(part):
+    """The first 2^24 samples of C2 in SNAPSHOT mode (B = 65536), binary32 GPU vs binary64
+    oracle, checked after every quarter (2^22 samples): each part resumes both runs where
+    the previous part left them (a part run alone first trains the earlier quarters)."""
+    lh = _lh()
+    B, quarter = 65536, 1 << 22
+    if "tr" not in _PREFIX:
+        g, _, _, _ = _c2()
+        t = oracle.Tables(g.n, g.src, g.dst, g.w)
+        _PREFIX["tr"] = trainer_for(g, d=128, K=5, orders=3, seed=2, total_samples=200_000_000, mode="snapshot",
+                                    batch=B)
+        _PREFIX["m"] = oracle.Model(t, d=128, K=5, orders=3, T=200_000_000, seed=2)
+        _PREFIX["done"] = 0
+    tr, m = _PREFIX["tr"], _PREFIX["m"]
+    while _PREFIX["done"] < (part + 1) * quarter:
+        first = _PREFIX["done"]
+        tr.train_steps(first, quarter)
+        m.train(first, quarter, "snapshot", B)
+        _PREFIX["done"] = first + quarter
+    tr.check()
     for name, tab, ref in (("U", lh.LH_TABLE_U, m.U), ("C", lh.LH_TABLE_C, m.C), ("U1", lh.LH_TABLE_U1, m.U1)):
         err = max_row_rel_err(tr.read(tab).cpu().numpy(), ref)
-        print(f"snapshot C2 prefix table {name}: max row rel err {err:.3e}", flush=True)
+        print(f"snapshot C2 prefix [0, {_PREFIX['done']}) table {name}: max row rel err {err:.3e}", flush=True)
         assert err <= 1e-5, (name, err)
 
 
@@ -279,7 +378,71 @@ def test_sampler_c2_sampled_indices():
     for first in (0, 199_999_000, 2**32 + 12345, 2**41 + 3):
         u, v, neg = tr.sample(first, 1000)
         ou, ov, oneg = oracle.sample(t, seed=2, graph_id=0, K=5, first=first, count=1000)
-        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(neg.cpu().numpy(), oneg)
+        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov)
+        assert np.array_equal(neg.cpu().numpy(), oneg)
+
+
+def _c5_graph_on_gpu():
+    import torch
+    from synth import CONFIGS
+    from synth.graphs import rmat_graph_gpu
+    c = CONFIGS["C5"]
+    src, dst, w = rmat_graph_gpu(c["scale"], c["n"], c["m_unique"], c["seed"])
+    torch.cuda.synchronize()
+    return c, src, dst, w
+
+
+def test_c5_negative_table_and_negatives_bitwise():
+    """C5's shape (directed R-MAT scale 26: 2^26 nodes, 2^30 arcs, lognormal weights): the
+    negative alias table over 2^26 nodes (out-degree^0.75, Eq. (1)) equals the oracle's bit
+    for bit, and the negatives of samples at 0, 2^32 and 2^41 + 3 are the oracle's.  (The
+    tables are d = 8 here: only the alias build and the sampler are under test.)"""
+    import time
+    lh = _lh()
+    t0 = time.time()
+    c, src, dst, w = _c5_graph_on_gpu()
+    print(f"C5 graph on the GPU in {time.time() - t0:.0f}s", flush=True)
+    tr = lh.Trainer(c["n"], src, dst, w, d=8, K=5, orders=2, dtype="bf16", seed=c["seed"], total_samples=10,
+                    init=False)
+    nthr, nal = tr.export_alias(lh.LH_ALIAS_NEG)
+    got = {first: tr.sample(first, 4096)[2].cpu().numpy() for first in (0, 2**32, 2**41 + 3)}
+    src_h = src.cpu().numpy()
+    tr.close()
+    del src, dst, w, tr
+    t0 = time.time()
+    deg = oracle.out_degree(src_h, c["n"])
+    del src_h
+    othr, oal = oracle.alias_build(oracle.neg_weights(deg))
+    print(f"oracle negative table over {c['n']} nodes in {time.time() - t0:.0f}s", flush=True)
+    assert np.array_equal(nal, oal) and np.array_equal(nthr, othr)
+    for first, neg in got.items():
+        ref = oracle.sample_negatives(c["n"], othr, oal, seed=c["seed"], graph_id=0, K=5, first=first, count=4096)
+        assert np.array_equal(neg, ref), first
+
+
+@pytest.mark.skipif(os.environ.get("LH_C5_EDGE") != "1",
+                    reason="about 75 GB of host memory and several minutes of oracle time: set LH_C5_EDGE=1")
+def test_c5_edge_table_and_tuples_bitwise():
+    """C5's 2^30-arc edge alias table equals the oracle's bit for bit, and whole tuples
+    (u, v, negatives) of samples at 0, 2^32 and 2^41 + 3 are the oracle's."""
+    import time
+    lh = _lh()
+    c, src, dst, w = _c5_graph_on_gpu()
+    tr = lh.Trainer(c["n"], src, dst, w, d=8, K=5, orders=2, dtype="bf16", seed=c["seed"], total_samples=10,
+                    init=False)
+    ethr, eal = tr.export_alias(lh.LH_ALIAS_EDGE)
+    got = {first: [x.cpu().numpy() for x in tr.sample(first, 4096)] for first in (0, 2**32, 2**41 + 3)}
+    host = [x.cpu().numpy() for x in (src, dst, w)]
+    tr.close()
+    del src, dst, w, tr
+    t0 = time.time()
+    t = oracle.Tables(c["n"], *host)
+    print(f"oracle tables over {t.m} arcs in {time.time() - t0:.0f}s", flush=True)
+    assert np.array_equal(eal, t.ealias) and np.array_equal(ethr, t.ethr)
+    del ethr, eal
+    for first, (u, v, neg) in got.items():
+        ou, ov, oneg = oracle.sample(t, seed=c["seed"], graph_id=0, K=5, first=first, count=4096)
+        assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(neg, oneg), first
 
 
 # ---------------------------------------------------------------------------
