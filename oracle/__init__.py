@@ -64,6 +64,12 @@ def lib():
         L.or_train.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
                                f64, f64, f64, u64, P, P, P, u64, u64, i32, u64]
         L.or_train.restype = i32
+        L.or_train_bf16.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
+                                    f64, f64, f64, u64, P, P, P, u64, u64, u64]
+        L.or_train_bf16.restype = i32
+        L.or_sr_bf16.argtypes = [f64, u32]
+        L.or_sr_bf16.restype = f64
+        L.or_bf16_rne.argtypes = [P, i64]
         L.or_train_hogwild_f32.argtypes = [P, P, i64, i64, P, P, P, P, u64, u32, i32, i32, i32,
                                            f64, f64, f64, u64, P, P, P, u64, u64, i32]
         L.or_train_hogwild_f32.restype = i32
@@ -203,14 +209,36 @@ def init_table(t: int, rows: int, d: int, seed: int, graph_id: int) -> np.ndarra
     return out
 
 
+def bf16_rne(x) -> np.ndarray:
+    """Nearest bfloat16 (ties to even) of the binary32 rounding of each value (float64 out)."""
+    y = _c(x, np.float64).copy()
+    lib().or_bf16_rne(_p(y), y.size)
+    return y
+
+
+def sr_bf16(x: float, bits: int) -> float:
+    """Stochastic rounding of x to bfloat16 with 16 given random bits (after rounding x to
+    binary32): the value the bfloat16 storage mode writes."""
+    return float(lib().or_sr_bf16(float(x), int(bits)))
+
+
 class Model:
-    """Embedding tables in binary64 plus the hyper-parameters of Algorithm 1."""
+    """Embedding tables plus the hyper-parameters of Algorithm 1.  ``storage``: "binary64"
+    (the default), or "bf16" -- tables held as bfloat16 values (initial values rounded to
+    nearest, every written value stochastically rounded; SEQ mode only), the precision
+    extension's storage.  ``sr_stream`` selects one of independent streams of rounding bits
+    (bfloat16 storage only)."""
 
     def __init__(self, tables: Tables, d: int, K: int, orders: int, T: int, seed: int,
-                 graph_id: int = 0, eta0: float = 0.025, lam: float = 0.0, alpha: float = 1.0):
+                 graph_id: int = 0, eta0: float = 0.025, lam: float = 0.0, alpha: float = 1.0,
+                 storage: str = "binary64", sr_stream: int = 0):
+        if storage not in ("binary64", "bf16"):
+            raise ValueError(storage)
         self.t, self.d, self.K, self.orders, self.T = tables, d, K, orders, T
         self.seed, self.graph_id = seed, graph_id
         self.eta0, self.lam, self.alpha = eta0, lam, alpha
+        self.storage = storage
+        self.sr_stream = int(sr_stream)
         n = tables.n
         self.U = self.C = self.U1 = None
         if orders & 2:
@@ -218,10 +246,25 @@ class Model:
             self.C = init_table(1, n, d, seed, graph_id).astype(np.float64)
         if orders & 1:
             self.U1 = init_table(2, n, d, seed, graph_id).astype(np.float64)
+        if storage == "bf16":
+            for X in (self.U, self.C, self.U1):
+                if X is not None:
+                    lib().or_bf16_rne(_p(X), X.size)
 
     def train(self, first: int, count: int, mode: str = "seq", batch: int = 0):
         """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch)."""
         t = self.t
+        if self.storage == "bf16":
+            if mode != "seq":
+                raise ValueError("bfloat16 storage is modelled in SEQ mode only")
+            rc = lib().or_train_bf16(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                                     _p(t.nthr), _p(t.nalias), self.seed, self.graph_id, self.d,
+                                     self.K, self.orders, self.eta0, self.lam, self.alpha, self.T,
+                                     _p(self.U), _p(self.C), _p(self.U1), first, count,
+                                     self.sr_stream)
+            if rc != 0:
+                raise ValueError("or_train_bf16 rejected its arguments")
+            return
         rc = lib().or_train(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
                             _p(t.nthr), _p(t.nalias), self.seed, self.graph_id, self.d, self.K,
                             self.orders, self.eta0, self.lam, self.alpha, self.T, _p(self.U),

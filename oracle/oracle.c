@@ -476,6 +476,106 @@ int or_train(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
 }
 
 /* ------------------------------------------------------------------------- */
+/* bfloat16 storage (the precision extension of the embedding tables): every   */
+/* value written to a table is the binary64 result rounded to binary32 (to     */
+/* nearest) and then stochastically to bfloat16 -- 16 random bits are added to */
+/* the binary32 pattern and the low 16 bits dropped, so the magnitude rounds up */
+/* with probability equal to its distance from the lower neighbour, in ulps    */
+/* (NaN stays a quiet NaN).  The bits come from Philox4x64-10 with key         */
+/* (seed, 2^34 | graph_id): the value written by write w of sample s (w = 16 o  */
+/* + slot, slot 0 the vertex row, 1 + j context slot j, o the order) to element */
+/* c uses 16-bit chunk c mod 16 of block (s, w, c / 16, stream); stream numbers */
+/* independent rounding streams of one run (0 by default).                     */
+/* ------------------------------------------------------------------------- */
+static double sr_bf16(double x, uint16_t r)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        u = (u | 0x00400000u) & 0xffff0000u;
+    } else {
+        u = (u + (uint32_t)r) & 0xffff0000u;
+    }
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* Exposed for the tests: the stochastic rounding of x with 16 given bits. */
+double or_sr_bf16(double x, uint32_t r) { return sr_bf16(x, (uint16_t)(r & 0xffffu)); }
+
+/* Nearest bfloat16 (ties to even) of the binary32 rounding of each x: the stored
+ * initial values. */
+void or_bf16_rne(double *x, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++) {
+        float f = (float)x[i];
+        uint32_t u;
+        memcpy(&u, &f, 4);
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            u = (u | 0x00400000u) & 0xffff0000u;
+        } else {
+            u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+        }
+        memcpy(&f, &u, 4);
+        x[i] = (double)f;
+    }
+}
+
+/* Add inc to row r of X in place, each element written as sr_bf16 with the bits of
+ * write w of sample s. */
+static void write_row_bf16(double *X, int64_t r, const double *inc, int d, uint64_t seed,
+                           uint32_t graph_id, uint64_t s, uint64_t w, uint64_t stream)
+{
+    uint64_t x[4] = {0, 0, 0, 0};
+    for (int c = 0; c < d; c++) {
+        if (c % 16 == 0) {
+            uint64_t ctr[4] = {s, w, (uint64_t)(c / 16), stream};
+            or_philox4x64_10(seed, (4ULL << 32) | graph_id, ctr, x);
+        }
+        uint16_t bits = (uint16_t)(x[(c % 16) / 4] >> (16 * (c % 4)));
+        X[r * d + c] = sr_bf16(X[r * d + c] + inc[c], bits);
+    }
+}
+
+/* SEQ mode with bfloat16 tables: or_train's mode 0 (the increments of a sample
+ * from the rows before it, in binary64), each row of each order written back
+ * through write_row_bf16 in the order vertex row, then context slots 0..K. */
+int or_train_bf16(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const uint64_t *nthr, const int32_t *nalias,
+                  uint64_t seed, uint32_t graph_id,
+                  int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+                  double *U, double *C, double *U1, uint64_t first, uint64_t count,
+                  uint64_t stream)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K};
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(K + 1));
+    double *dA = (double *)malloc(sizeof(double) * (size_t)d);
+    double *dB = (double *)malloc(sizeof(double) * (size_t)d * (size_t)(K + 1));
+    for (uint64_t s = first; s < first + count; s++) {
+        int32_t u;
+        draw_tuple(&g, s, &u, &ids[0], &ids[1]);
+        double eta = eta0 * (1.0 - (double)s / (double)T);
+        for (int o = 2; o >= 1; o--) {
+            if (!(orders & o)) continue;
+            double *A = o == 2 ? U : U1, *B = o == 2 ? C : U1;
+            sample_increments(&h, eta, A, B, u, ids, dA, dB);
+            write_row_bf16(A, u, dA, d, seed, graph_id, s, (uint64_t)(16 * o), stream);
+            for (int j = 0; j <= K; j++)
+                write_row_bf16(B, ids[j], dB + (size_t)j * (size_t)d, d, seed, graph_id, s,
+                               (uint64_t)(16 * o + 1 + j), stream);
+        }
+    }
+    free(ids); free(dA); free(dB);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Timing mode: the same per-sample rule in binary32, samples spread over     */
 /* OpenMP threads with no locking (Hogwild).  Rows are read, increments are    */
 /* computed from what was read, and the increments are added back; updates    */

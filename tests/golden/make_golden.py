@@ -3,6 +3,7 @@
     python tests/golden/make_golden.py c1_auc    # seconds
     python tests/golden/make_golden.py c2_auc    # about 35 minutes, single thread
     python tests/golden/make_golden.py batch6_auc  # about a minute
+    python tests/golden/make_golden.py batch6_bf16_auc  # about five minutes (bfloat16 storage, 8 streams)
     python tests/golden/make_golden.py mid_auc     # about a minute
 
 Each output JSON records the command, the workload and the oracle's binary64 result.
@@ -55,22 +56,36 @@ def run_auc(name: str, orders: int, T: int, d: int, out: str):
     print(json.dumps(res))
 
 
-def run_batch6(out: str):
+def run_batch6(out: str, storage: str = "binary64"):
     """Second-order held-out AUCs (uc, uu) of the six small graphs of the batched-launch
-    tests, each trained alone in SEQ mode with its own seed and graph id."""
+    tests, each trained alone in SEQ mode with its own seed and graph id; binary64 tables,
+    or bfloat16 tables with every write stochastically rounded (storage="bf16")."""
     t0 = time.time()
-    res = {"graphs": [], "K": 5, "orders": 2, "mode": "seq", "precision": "binary64",
+    res = {"graphs": [], "K": 5, "orders": 2, "mode": "seq",
+           "precision": "binary64" if storage == "binary64" else
+           "binary64 arithmetic, bfloat16 tables (nearest-rounded initial values, stochastically rounded writes)",
            "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    streams = 1 if storage == "binary64" else 8
+    if streams > 1:
+        res["rounding_streams"] = streams
+        res["note"] = ("auc_uc / auc_uu: mean over the independent rounding streams 0..7; "
+                       "sd_*: their sample standard deviation")
     for it in small_batch(6):
         g, hs, hd, neg = it["graph"], it["held_src"], it["held_dst"], it["neg_dst"]
         tb = oracle.Tables(g.n, g.src, g.dst, g.w)
-        m = oracle.Model(tb, d=it["d"], K=5, orders=2, T=it["T"], seed=it["seed"], graph_id=it["graph_id"])
-        m.train(0, it["T"], "seq")
-        res["graphs"].append({
-            "graph_id": it["graph_id"], "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": it["d"],
-            "T": it["T"], "seed": it["seed"],
-            "auc_uc": oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2)),
-            "auc_uu": oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg))})
+        uc, uu = [], []
+        for stream in range(streams):
+            m = oracle.Model(tb, d=it["d"], K=5, orders=2, T=it["T"], seed=it["seed"],
+                             graph_id=it["graph_id"], storage=storage, sr_stream=stream)
+            m.train(0, it["T"], "seq")
+            uc.append(oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2)))
+            uu.append(oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg)))
+        rec = {"graph_id": it["graph_id"], "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": it["d"],
+               "T": it["T"], "seed": it["seed"], "auc_uc": float(np.mean(uc)), "auc_uu": float(np.mean(uu))}
+        if streams > 1:
+            rec.update(sd_uc=float(np.std(uc, ddof=1)), sd_uu=float(np.std(uu, ddof=1)), streams_uc=uc,
+                       streams_uu=uu)
+        res["graphs"].append(rec)
         print(res["graphs"][-1], flush=True)
     res["oracle_seconds"] = round(time.time() - t0, 1)
     with open(os.path.join(HERE, out), "w") as f:
@@ -104,6 +119,8 @@ if __name__ == "__main__":
         run_auc("C2", orders=3, T=CONFIGS["C2"]["T"], d=CONFIGS["C2"]["d"], out="c2_oracle_auc.json")
     elif which == "batch6_auc":
         run_batch6("batch6_oracle_auc.json")
+    elif which == "batch6_bf16_auc":
+        run_batch6("batch6_oracle_bf16_auc.json", storage="bf16")
     elif which == "mid_auc":
         run_mid("mid_oracle_auc.json")
     else:

@@ -159,14 +159,13 @@ def _small_batch(G=6, dtype="bf16"):
     return items
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
-def test_batched_launch_trains_every_sample_once_and_matches_oracle(dtype):
-    """Six graphs in one launch: every graph's [0, T) is trained exactly once, and each
-    graph's held-out AUCs match the binary64 oracle trained on that graph alone (binary32
-    tables, and bfloat16 tables with stochastic rounding, as in the batched workload)."""
+def test_batched_launch_trains_every_sample_once_and_matches_oracle():
+    """Six binary32 graphs in one launch: every graph's [0, T) is trained exactly once, and
+    each graph's held-out AUCs match the binary64 oracle trained on that graph alone
+    within 0.005."""
     lh = _lh()
     gold = json.load(open(os.path.join(GOLDEN, "batch6_oracle_auc.json")))["graphs"]
-    items = _small_batch(dtype=dtype)
+    items = _small_batch(dtype="fp32")
     bt = lh.BatchTrainer([it[-1] for it in items])
     bt.run()
     assert bt.done() == [it[4] for it in items]
@@ -175,9 +174,51 @@ def test_batched_launch_trains_every_sample_once_and_matches_oracle(dtype):
         uc, uu = _auc_uc_uu(tr, hs, hd, neg)
         ref = gold[gi]
         assert ref["graph_id"] == gi and ref["T"] == T and ref["m_train"] == g.m
-        print(f"{dtype} graph {gi} (n={g.n}, d={d}): batched uc {uc:.4f} (oracle {ref['auc_uc']:.4f}) "
+        print(f"fp32 graph {gi} (n={g.n}, d={d}): batched uc {uc:.4f} (oracle {ref['auc_uc']:.4f}) "
               f"uu {uu:.4f} (oracle {ref['auc_uu']:.4f})", flush=True)
         assert abs(uc - ref["auc_uc"]) <= 0.005 and abs(uu - ref["auc_uu"]) <= 0.005
+
+
+def test_batched_bf16_matches_the_oracle_with_bf16_tables():
+    """The same six graphs with bfloat16 tables in one launch, against the oracle with
+    bfloat16 tables (SEQ, binary64 arithmetic, every write stochastically rounded): on these
+    small graphs trained for 20 epochs the rounding itself moves uc by 0.007 to 0.017 from
+    the binary64 oracle (the oracle's own bfloat16 runs show it, with no concurrency), and
+    makes each run's AUC a random draw with a spread sd_g measured over 8 independent
+    rounding streams.  One GPU run is one such draw, so per graph the AUCs must lie within
+    0.005 + 3 sd_g sqrt(1 + 1/8) of the oracle's mean (a 0.3 % false-alarm bound for a
+    draw of the same distribution), and the mean over the six graphs of the differences
+    within 0.005 + 3 sqrt(sum sd_g^2 (1 + 1/8)) / 6."""
+    lh = _lh()
+    gold = json.load(open(os.path.join(GOLDEN, "batch6_oracle_bf16_auc.json")))
+    assert gold["rounding_streams"] == 8
+    gold = gold["graphs"]
+    b64 = json.load(open(os.path.join(GOLDEN, "batch6_oracle_auc.json")))["graphs"]
+    items = _small_batch(dtype="bf16")
+    bt = lh.BatchTrainer([it[-1] for it in items])
+    bt.run()
+    assert bt.done() == [it[4] for it in items]
+    diffs = {"uc": [], "uu": []}
+    var = {"uc": 0.0, "uu": 0.0}
+    for gi, (g, hs, hd, neg, T, d, tr) in enumerate(items):
+        tr.check()
+        got = dict(zip(("uc", "uu"), _auc_uc_uu(tr, hs, hd, neg)))
+        ref = gold[gi]
+        assert ref["graph_id"] == gi and ref["T"] == T and ref["m_train"] == g.m
+        for k in ("uc", "uu"):
+            sd = ref["sd_" + k]
+            tol = 0.005 + 3.0 * sd * (1.0 + 1.0 / 8.0) ** 0.5
+            print(f"bf16 graph {gi} (n={g.n}, d={d}) {k}: batched {got[k]:.4f}, oracle bf16 tables "
+                  f"{ref['auc_' + k]:.4f} (sd {sd:.4f}, bar {tol:.4f}), oracle binary64 {b64[gi]['auc_' + k]:.4f}",
+                  flush=True)
+            assert abs(got[k] - ref["auc_" + k]) <= tol, (gi, k, got[k], ref["auc_" + k], tol)
+            diffs[k].append(got[k] - ref["auc_" + k])
+            var[k] += sd * sd * (1.0 + 1.0 / 8.0)
+    for k in ("uc", "uu"):
+        mean_diff = sum(diffs[k]) / len(diffs[k])
+        bar = 0.005 + 3.0 * var[k] ** 0.5 / len(diffs[k])
+        print(f"bf16 {k}: mean difference over the graphs {mean_diff:+.4f} (bar {bar:.4f})", flush=True)
+        assert abs(mean_diff) <= bar
 
 
 def test_batched_launch_on_the_callers_stream():
