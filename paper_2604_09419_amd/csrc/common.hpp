@@ -115,11 +115,26 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f)
     return (u + 0x7fffu + lsb) >> 16;
 }
 
-__device__ __forceinline__ uint32_t f32_to_bf16_sr(float f, uint32_t rnd16)
+// Two binary32 values as one packed bfloat16 pair, element 0 in the low half.
+// Stochastic rounding: element 0 adds bits 0-15 of rnd to its binary32 pattern and keeps
+// the high half, element 1 adds bits 16-31 (NaN stays NaN).  gfx950's v_cvt_sr_bf16_f32
+// adds the high 16 bits of its random operand (measured on MI355X for every finite input,
+// denormals included), one instruction per element.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bf16x2_sr(float x0, float x1, uint32_t rnd)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    return (u + (rnd16 & 0xffffu)) >> 16;
+    bf16x2_t v = {};
+    v = __builtin_amdgcn_cvt_sr_bf16_f32(v, x0, rnd << 16, false);
+    v = __builtin_amdgcn_cvt_sr_bf16_f32(v, x1, rnd, true);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Round to nearest even: one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t bf16x2_rne(float x0, float x1)
+{
+    const bf16x2_t v = {(__bf16)x0, (__bf16)x1};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // ---------------------------------------------------------------------------

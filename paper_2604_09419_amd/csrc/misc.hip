@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(256) k_shadow_store(ShadowDev a, long long bou
         const int qi = (un % 8) / 2;
         const unsigned long long wd = qi == 0 ? q.x : qi == 1 ? q.y : qi == 2 ? q.z : q.w;
         const uint32_t rnd = (uint32_t)(wd >> (32 * (un % 2)));
-        a.tab[t][r * per + un] = f32_to_bf16_sr(x.x, rnd) | (f32_to_bf16_sr(x.y, rnd >> 16) << 16);
+        a.tab[t][r * per + un] = bf16x2_sr(x.x, x.y, rnd);
     }
 }
 

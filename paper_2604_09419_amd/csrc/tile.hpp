@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t f32_to_unit(const float (&x)[Elem<TT>::EPU],
     if constexpr (sizeof(TT) == 4) {
         return __float_as_uint(x[0]);
     } else {
-        return f32_to_bf16_sr(x[0], rnd) | (f32_to_bf16_sr(x[1], rnd >> 16) << 16);
+        return bf16x2_sr(x[0], x[1], rnd);
     }
 }
 
@@ -122,7 +122,9 @@ struct SnapOut {
 // Sum over an aligned group of LPS lanes, every lane receiving the sum.  Within a row
 // of 16 lanes the butterfly uses DPP: quad_perm [1,0,3,2] and [2,3,0,1] (xor 1, 2), then
 // row_half_mirror and row_mirror, which pair each lane with a lane of the other half
-// once the halves are uniform.  Across rows: ds_swizzle xor 16, then a shuffle xor 32.
+// once the halves are uniform.  Across rows, gfx950's lane swaps (v_permlane16_swap: rows
+// 0 <-> 1 and 2 <-> 3; v_permlane32_swap: the two halves of the wavefront) give each
+// lane its partner's value in one VALU instruction, with no LDS round trip.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x)
 {
@@ -136,9 +138,16 @@ __device__ __forceinline__ float group_sum(float x)
     if constexpr (LPS >= 4) x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
     if constexpr (LPS >= 8) x += dpp_mov<0x141>(x);  // row_half_mirror
     if constexpr (LPS >= 16) x += dpp_mov<0x140>(x); // row_mirror
-    if constexpr (LPS >= 32)
-        x += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
-    if constexpr (LPS >= 64) x += __shfl_xor(x, 32);
+    if constexpr (LPS >= 32) {
+        // swapping a register with itself leaves the partner row's value in one of the two
+        // results and this lane's own value in the other, so their sum is the pair's sum
+        const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+        x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
+    if constexpr (LPS >= 64) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+        x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
     return x;
 }
 
@@ -165,7 +174,6 @@ __device__ __forceinline__ float group_lane(float x, int j)
     }
 }
 
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
 // Element e of a unit as binary32.
@@ -199,7 +207,9 @@ __device__ __forceinline__ void store_coherent(uint32_t *p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <typename TT, int LPS, int UPL>
+// FULL: the shape covers the row exactly (LPS * UPL == units per row), so no access needs
+// a bounds mask and the loads and stores of a sample are straight-line code.
+template <typename TT, int LPS, int UPL, bool FULL>
 __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint32_t (&o)[UPL])
 {
     const uint32_t *w = reinterpret_cast<const uint32_t *>(row);
@@ -207,7 +217,7 @@ __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint
     for (int k = 0; k < UPL; ++k) {
         const int un = k * LPS + gl;
         uint32_t v = 0u;
-        if (un < nunits) v = load_coherent(w + un);
+        if (FULL || un < nunits) v = load_coherent(w + un);
         o[k] = v;
     }
 }
@@ -220,13 +230,13 @@ __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint
 // and nothing here uses the loaded words, so every row's loads of a sample are in flight
 // together; shadow rows are packed afterwards by pack_shadow_row.  SH: the kernel may meet
 // shadow rows (else ids are never negative and hi stays untouched).
-template <typename TT, int LPS, int UPL, bool SH>
+template <typename TT, int LPS, int UPL, bool SH, bool FULL>
 __device__ __forceinline__ void load_row_raw(const GraphDev &g, int t, int id, int gl, uint32_t (&lo)[UPL],
                                              uint32_t (&hi)[UPL])
 {
     const int nu = g.nunits;
     if constexpr (sizeof(TT) == 4 || !SH) {
-        load_row<TT, LPS, UPL>((const TT *)g.tab[t] + (long long)id * g.d, nu, gl, lo);
+        load_row<TT, LPS, UPL, FULL>((const TT *)g.tab[t] + (long long)id * g.d, nu, gl, lo);
     } else {
         const bool sh = id < 0;
         const uint32_t *tw = reinterpret_cast<const uint32_t *>((const TT *)g.tab[t] + (long long)(sh ? 0 : id) * g.d);
@@ -248,22 +258,22 @@ __device__ __forceinline__ void pack_shadow_row(int id, uint32_t (&lo)[UPL], con
     if constexpr (sizeof(TT) == 2 && SH) {
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
-            const uint32_t p = f32_to_bf16_rne(__uint_as_float(lo[k])) | (f32_to_bf16_rne(__uint_as_float(hi[k])) << 16);
+            const uint32_t p = bf16x2_rne(__uint_as_float(lo[k]), __uint_as_float(hi[k]));
             lo[k] = id < 0 ? p : lo[k];
         }
     }
 }
 
-template <typename TT, int LPS, int UPL, int KMAX, bool SH>
+template <typename TT, int LPS, int UPL, int KMAX, bool SH, bool FULL>
 __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev &g, int tA, int tB, int u,
                                           const int (&ids)[KMAX + 1], int K, int gl)
 {
     uint32_t ah[UPL], bh[KMAX + 1][UPL];
-    load_row_raw<TT, LPS, UPL, SH>(g, tA, u, gl, r.a, ah);
+    load_row_raw<TT, LPS, UPL, SH, FULL>(g, tA, u, gl, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j <= K) {
-            load_row_raw<TT, LPS, UPL, SH>(g, tB, ids[j], gl, r.b[j], bh[j]);
+            load_row_raw<TT, LPS, UPL, SH, FULL>(g, tB, ids[j], gl, r.b[j], bh[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < UPL; ++k) r.b[j][k] = bh[j][k] = 0u;
@@ -275,31 +285,31 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
         if (j <= K) pack_shadow_row<TT, UPL, SH>(ids[j], r.b[j], bh[j]);
 }
 
-// Stochastic-rounding bits of unit un of a row: a Weyl step from the row's seed and one
-// xor-shift, full-rate integer operations only (the 32-bit multiplies of a hash run at a
-// quarter of the rate, and this kernel is bound by its vector instruction issue).  The
-// row seeds of a sample come from one lowbias32 hash per sample and order (sgd_order); any
-// fixed function of a uniformly distributed seed keeps every rounding unbiased.  The bits
-// depend on the unit, not on the lane holding it, so every tile shape rounds alike.
+// Stochastic-rounding bits of unit un of a row: a Weyl step from the row's seed, one
+// integer add once the lane's multiple of the step is formed.  Element 0 of the unit
+// rounds with the low 16 bits, element 1 with the high 16 bits.  The row seeds of a
+// sample come from one lowbias32 hash per sample and order (sgd_order), so each half is
+// uniformly distributed and every rounding is unbiased.  The bits depend on the unit, not
+// on the lane holding it, so every tile shape rounds alike.
 __device__ __forceinline__ uint32_t sr_bits(uint32_t rseed, int un)
 {
-    const uint32_t x = rseed + (uint32_t)un * 0x9E3779B9u;
-    return x ^ (x >> 16);
+    return rseed + (uint32_t)un * 0x9E3779B9u;
 }
 
 // Write one row back: new = old + inc.  `hot` asks for the atomic path.
 //   binary32: stored, or atomic increments;
-//   bfloat16 table rows (id >= 0): with the random bits of unit un being
-//   mix(rseed + un * phi), mix(x) = x ^ (x >> 16), a cold row is stored as the stochastic
-//   rounding SR(old + inc); a hot row receives, by packed bfloat16 atomic adds, the
-//   increments SR(old + inc) - old rounded to nearest (units whose increments are both zero
-//   are skipped).  While old and SR(old + inc) are within a factor of two of each other
-//   (always when |inc| <= |old| / 2) that difference is exact, and where no other write
-//   changed the unit since it was loaded the atomic result is SR(old + inc) bit for bit, the
-//   value a cold store would have written; near zero it may be one bfloat16 spacing off.
-//   A concurrent change receives the increment on top.  Shadow rows (id < 0, even elements
-//   then odd ones) get binary32 atomic increments.
-template <typename TT, int LPS, int UPL, bool SH>
+//   bfloat16 table rows (id >= 0): with the random bits of unit un being rseed + un * phi
+//   (element 0 rounds with its low half, element 1 with its high half), a cold row is
+//   stored as the stochastic rounding SR(old + inc); a hot row receives, by packed bfloat16
+//   atomic adds, the increments SR(old + inc) - old rounded to nearest (units whose
+//   increments are both zero are skipped, except in a dry run).  While old and
+//   SR(old + inc) are within a factor of two of each other (always when |inc| <= |old| / 2)
+//   that difference is exact, and where no other write changed the unit since it was
+//   loaded the atomic result is SR(old + inc) bit for bit, the value a cold store would have
+//   written; near zero it may be one bfloat16 spacing off.  A concurrent change receives the
+//   increment on top.  Shadow rows (id < 0, even elements then odd ones) get binary32
+//   atomic increments.
+template <typename TT, int LPS, int UPL, bool SH, bool FULL>
 __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int gl, const uint32_t (&old)[UPL],
                                           const float (&inc)[UPL][Elem<TT>::EPU], bool hot, uint32_t rseed)
 {
@@ -311,32 +321,28 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
                 const int un = k * LPS + gl;
-                if (un < nunits) atomicAdd(sw + un, inc[k][0]);
+                if (FULL || un < nunits) atomicAdd(sw + un, inc[k][0]);
             }
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
                 const int un = k * LPS + gl;
-                if (un < nunits) atomicAdd(sw + nunits + un, inc[k][1]);
+                if (FULL || un < nunits) atomicAdd(sw + nunits + un, inc[k][1]);
             }
             return;
         }
         if (hot) {
             uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
+            // (a dry run, step size scaled to zero, issues every atomic, so that a timing run
+            // pays for the hot set as training does)
+            const bool all = g.eta_scale == 0.0f;
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
                 const int un = k * LPS + gl;
-                if (un < nunits) {
-                    const uint32_t rnd = sr_bits(rseed, un);
-                    uint32_t p = 0u;
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const float o = val<TT>(old[k], e);
-                        const float nv = __uint_as_float(f32_to_bf16_sr(o + inc[k][e], rnd >> (16 * e)) << 16);
-                        p |= f32_to_bf16_rne(nv - o) << (16 * e);
-                    }
-                    // (a dry run, step size scaled to zero, issues them all, so that a
-                    // timing run pays for the hot set as training does)
-                    if ((p & 0x7fff7fffu) != 0u || g.eta_scale == 0.0f)
+                if (FULL || un < nunits) {
+                    const float o0 = val<TT>(old[k], 0), o1 = val<TT>(old[k], 1);
+                    const uint32_t nv = bf16x2_sr(o0 + inc[k][0], o1 + inc[k][1], sr_bits(rseed, un));
+                    const uint32_t p = bf16x2_rne(val<TT>(nv, 0) - o0, val<TT>(nv, 1) - o1);
+                    if ((p & 0x7fff7fffu) != 0u || all)
                         __builtin_amdgcn_global_atomic_fadd_v2bf16(
                             (short2_t __attribute__((address_space(1))) *)(w + un),
                             __builtin_bit_cast(short2_t, p));
@@ -350,7 +356,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const int un = k * LPS + gl;
-            if (un < nunits) {
+            if (FULL || un < nunits) {
                 float x[EPU];
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) x[e] = val<TT>(old[k], e) + inc[k][e];
@@ -363,7 +369,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const int un = k * LPS + gl;
-            if (un < nunits) atomicAdd(reinterpret_cast<float *>(w) + un, inc[k][0]);
+            if (FULL || un < nunits) atomicAdd(reinterpret_cast<float *>(w) + un, inc[k][0]);
         }
     }
 }
@@ -372,7 +378,7 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 // the context rows (the same table for first order).  ids[0] = v, ids[1..K] = negatives
 // (bfloat16 Hogwild: ~slot for rows in the shadow).  hot: bit 0 for the vertex row,
 // bit 1 + j for slot j.
-template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP, bool SH>
+template <typename TT, int LPS, int UPL, int KMAX, bool FIRST, bool SNAP, bool SH, bool FULL>
 __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&ids)[KMAX + 1], int K, float eta,
                                           unsigned dupb, unsigned dupu, unsigned hot, uint32_t sr, int oi, int gl,
                                           const SnapOut &so, unsigned long long s, int tabA, int tabB,
@@ -484,7 +490,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         constexpr uint32_t kSlot = 0x632BE59Bu;
         (void)oi;
         // vertex row
-        write_row<TT, LPS, UPL, SH>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, seed + kSlot);
+        write_row<TT, LPS, UPL, SH, FULL>(g, tabA, u, gl, a, dA, (atom & 1u) != 0, seed + kSlot);
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
@@ -494,7 +500,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
             for (int k = 0; k < UPL; ++k)
 #pragma unroll
                 for (int e = 0; e < EPU; ++e) inc[k][e] = gj[j] * val<TT>(a[k], e) - el * val<TT>(b[j][k], e);
-            write_row<TT, LPS, UPL, SH>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0,
+            write_row<TT, LPS, UPL, SH, FULL>(g, tabB, ids[j], gl, b[j], inc, (atom & (2u << j)) != 0,
                                         seed + (uint32_t)(j + 2) * kSlot);
         }
     }
@@ -503,7 +509,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
 // One tile of 64 samples [tile, min(tile + 64, end)).  UPL units per lane.  SH: bfloat16
 // Hogwild with a binary32 shadow of the hot rows (compiled out otherwise: the shadow's
 // address choice and second-half loads cost a quarter of the kernel's speed even unused).
-template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SNAP, bool SH>
+template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SNAP, bool SH, bool FULL = false>
 __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long tile, unsigned long long end,
                                          const SnapOut &so)
 {
@@ -612,17 +618,17 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
         // 2 (2 + K) rows per sample are in flight at once.
         Rows<TT, UPL, KMAX> r2, r1;
         if constexpr ((ORD & 2) != 0)
-            load_rows<TT, LPS, UPL, KMAX, SH>(r2, g, LH_TABLE_U, LH_TABLE_C, u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX, SH, FULL>(r2, g, LH_TABLE_U, LH_TABLE_C, u, ids, K, gl);
         if constexpr ((ORD & 1) != 0)
-            load_rows<TT, LPS, UPL, KMAX, SH>(r1, g, LH_TABLE_U1, LH_TABLE_U1, u, ids, K, gl);
+            load_rows<TT, LPS, UPL, KMAX, SH, FULL>(r1, g, LH_TABLE_U1, LH_TABLE_U1, u, ids, K, gl);
         int oi = 0;
         if constexpr ((ORD & 2) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, false, SNAP, SH>(g, u, ids, K, eta, dupb, dupu, hot, sr, oi, gl, so, s,
+            sgd_order<TT, LPS, UPL, KMAX, false, SNAP, SH, FULL>(g, u, ids, K, eta, dupb, dupu, hot, sr, oi, gl, so, s,
                                                        LH_TABLE_U, LH_TABLE_C, r2);
             ++oi;
         }
         if constexpr ((ORD & 1) != 0) {
-            sgd_order<TT, LPS, UPL, KMAX, true, SNAP, SH>(g, u, ids, K, eta, dupb, dupu, hot, sr ^ 0x5bd1e995u, oi, gl,
+            sgd_order<TT, LPS, UPL, KMAX, true, SNAP, SH, FULL>(g, u, ids, K, eta, dupb, dupu, hot, sr ^ 0x5bd1e995u, oi, gl,
                                                       so, s, LH_TABLE_U1, LH_TABLE_U1, r1);
         }
     }
