@@ -144,6 +144,16 @@ LH_API lh_status lh_set_graph(lh_handle *h, int64_t n, int64_t m, const int32_t 
  * is zero (or m == 0). */
 LH_API lh_status lh_build_alias(lh_handle *h, void *scratch, size_t scratch_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lh_build_alias without the scratch
+ * argument.  The binary64 build arrays live in a 65 MiB array the library holds on each
+ * GPU it runs on from its load to the end of the process, so the call allocates nothing;
+ * it accepts graphs with n <= 2^21 and m <= 2^21 (LH_ERR_INVALID_ARG, before any GPU
+ * work, for larger ones).  Results, synchronisation and errors as lh_build_alias.  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on one GPU (from two host
+ * threads, or on two streams) race and must not be made. */
+LH_API lh_status lh_build_alias_noalloc(lh_handle *h);
+
 /* Replace (import) or copy out (export) one alias table, the encoding of the edge
  * distribution of Algorithm 3 (which = LH_ALIAS_EDGE, N = m) or of the negative
  * distribution of Eq. (1) (LH_ALIAS_NEG, N = n): column c keeps itself when a draw's

@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         "lh_bind": [P, P, sz, ctypes.POINTER(ctypes.c_void_p * 3), P],
         "lh_set_graph": [P, i64, i64, P, P, P],
         "lh_build_alias": [P, P, sz],
+        "lh_build_alias_noalloc": [P],
         "lh_import_alias": [P, S, P, P],
         "lh_export_alias": [P, S, P, P],
         "lh_init_embeddings": [P],
@@ -152,6 +153,10 @@ def lh_set_graph(h, n: int, m: int, src_ptr: int, dst_ptr: int, w_ptr: int):
 
 def lh_build_alias(h, scratch_ptr: int, nbytes: int):
     check(lib().lh_build_alias(h, scratch_ptr or None, nbytes), "lh_build_alias", h)
+
+
+def lh_build_alias_noalloc(h):
+    check(lib().lh_build_alias_noalloc(h), "lh_build_alias_noalloc", h)
 
 
 def lh_import_alias(h, which: int, thr_ptr: int, alias_ptr: int):

@@ -15,6 +15,7 @@
 //   thr = prob >= 1 ? 2^64 - 1 : (uint64)(prob 2^64)
 // Every step is a single correctly rounded binary64 operation in a fixed order, so
 // the tables are bitwise reproducible.
+#include <mutex>
 #include <vector>
 
 #include "handle.hpp"
@@ -22,7 +23,43 @@
 
 #pragma clang fp contract(off)
 
+// Build scratch of lh_build_alias_noalloc, for callers that cannot allocate: one array
+// per GPU, held from the library's load to the end of the process.  Host code never uses
+// this name as an address (in host code it names a host-side stand-in); it uses the
+// device address hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[lh::kNoAllocScratchBytes];
+
 namespace lh {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+// Once per device, with that device current: the device address of `scratch` there.
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_err[device];
+}
+
+static void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_done[device] ? g_scratch_ptr[device] : nullptr;
+}
 
 // ---------------------------------------------------------------------------
 // Validation of the arcs: endpoints in [0, n), weights finite and >= 0.
@@ -449,3 +486,33 @@ lh_status export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias)
 }
 
 }  // namespace lh
+
+// The alias build of lh_build_alias with its scratch in the static per-device array
+// instead of a caller's workspace: the same kernels, handed the array's device address.
+// The kernels clear what they accumulate into (degrees, histogram) themselves, and every
+// other scratch word is written before it is read, so the contents a previous call left
+// do not matter.  Two such calls that overlap on one GPU (two host threads, two streams)
+// race on the array.
+extern "C" lh_status lh_build_alias_noalloc(lh_handle *h)
+{
+    if (!h) return LH_ERR_INVALID_ARG;
+    if (!h->graph_set) return lh::fail(h, LH_ERR_NOT_BUILT, "lh_set_graph first");
+    if (h->m < 1) return lh::fail(h, LH_ERR_ZERO_WEIGHT, "the graph has no arcs");
+    // The documented limits; scratch_layout(2^21, 2^21) is 64.03 MiB, within the array.
+    const lh::ScratchLayout L = lh::scratch_layout(h->n, h->m);
+    if (h->n > lh::kNoAllocMaxItems || h->m > lh::kNoAllocMaxItems || L.total > lh::kNoAllocScratchBytes)
+        return lh::fail(h, LH_ERR_INVALID_ARG,
+                        "graph too large for the static build scratch (65 MiB: n and m up to 2^21 each)");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != h->device) (void)hipSetDevice(h->device);
+    lh_status st = LH_OK;
+    hipError_t e = lh::noalloc_scratch_setup(h->device);
+    void *ptr = lh::noalloc_scratch(h->device);
+    if (e != hipSuccess || !ptr)
+        st = lh::hip_fail(h, e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+    else
+        st = lh::build_alias(h, ptr, lh::kNoAllocScratchBytes);
+    if (prev >= 0 && prev != h->device) (void)hipSetDevice(prev);
+    return st;
+}

@@ -114,7 +114,7 @@ static bool table_used(const lh_handle *h, int t)
 using namespace lh;
 
 static const char *const kSymbols[] = {
-    "lh_create",          "lh_workspace_size", "lh_bind",          "lh_set_graph",       "lh_build_alias",
+    "lh_create",          "lh_workspace_size", "lh_bind",          "lh_set_graph",       "lh_build_alias",     "lh_build_alias_noalloc",
     "lh_import_alias",    "lh_export_alias",   "lh_init_embeddings", "lh_sample",        "lh_train_steps",
     "lh_read_embeddings", "lh_write_embeddings", "lh_check",       "lh_last_train_ms",   "lh_tune",   "lh_kernel_config", "lh_set_kernel_config",
     "lh_status_string",   "lh_last_error",     "lh_destroy",       "lh_batch_create",    "lh_batch_tune",
@@ -178,6 +178,9 @@ lh_status lh_create(lh_handle **out, const lh_params *p, int device)
         return LH_ERR_HIP;
     }
     h->cfg = default_cfg(p->dtype, p->d);
+    // The static scratch of lh_build_alias_noalloc: its address on this device, looked up
+    // once per device here at set-up (a failure is reported by that call, not here).
+    (void)noalloc_scratch_setup(device);
     *out = h;
     return LH_OK;
 }

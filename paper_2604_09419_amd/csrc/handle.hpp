@@ -98,6 +98,13 @@ inline double small_table_window(double l2_bytes, double footprint)
 
 ScratchLayout scratch_layout(long long n, long long m);
 
+// Bytes of the static build scratch of lh_build_alias_noalloc (per GPU): enough for
+// scratch_layout(n, m) with n, m <= 2^21.
+constexpr size_t kNoAllocScratchBytes = 65ull << 20;
+constexpr long long kNoAllocMaxItems = 1ll << 21;  // largest n and largest m it accepts
+// Look up that array's device address on `device` (current) once; lh_create calls it.
+hipError_t noalloc_scratch_setup(int device);
+
 constexpr int RADIX_ITEMS = 16;
 constexpr int RADIX_THREADS = 256;
 constexpr int RADIX_TILE = RADIX_ITEMS * RADIX_THREADS;
