@@ -257,11 +257,13 @@ __global__ void __launch_bounds__(256, (batch_min_waves<TT, SH>())) k_batch(Batc
         unsigned long long s0 = chunk * a.item_samples;
         unsigned long long s1 = s0 + a.item_samples;
         if (s1 > D.limit) s1 = D.limit;
-        // rows that one of the two tiles covers exactly take it without bounds masks
-        if (g.nunits == Cfg::LS * Cfg::US) {
+        // rows that one of the two tiles covers exactly take it without bounds masks (graphs
+        // with KMAX negatives)
+        const bool kfull = g.K == KMAX;
+        if (kfull && g.nunits == Cfg::LS * Cfg::US) {
             for (unsigned long long t = s0; t < s1; t += 64)
                 sgd_tile<TT, Cfg::LS, Cfg::US, KMAX, 2, false, SH, true>(g, t, s1, so);
-        } else if (g.nunits == Cfg::LL * Cfg::UL) {
+        } else if (kfull && g.nunits == Cfg::LL * Cfg::UL) {
             for (unsigned long long t = s0; t < s1; t += 64)
                 sgd_tile<TT, Cfg::LL, Cfg::UL, KMAX, 2, false, SH, true>(g, t, s1, so);
         } else {

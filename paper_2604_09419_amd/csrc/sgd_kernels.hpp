@@ -20,8 +20,8 @@ constexpr int hogwild_min_waves() { return sizeof(TT) == 2 ? 5 : 3; }
 // wavefront takes 64-sample tiles from the launch's tile counter (g.tiles, zero at launch)
 // until none are left, so wavefronts that meet slow rows do not hold up a fixed share of
 // the work and the grid is only as large as what is resident.
-// FULL: the tile shape covers a row exactly (lanes x units == the row's units), so row
-// accesses need no bounds mask.
+// FULL: the tile shape covers a row exactly (lanes x units == the row's units) and K == KMAX,
+// so row accesses need no bounds mask or slot test.
 template <typename TT, int LPS, int UPL, int KMAX, int ORD, bool SH, bool FULL = false>
 __global__ void __launch_bounds__(256, hogwild_min_waves<TT>()) k_hogwild(GraphDev g, unsigned long long first, unsigned long long end)
 {
@@ -181,7 +181,7 @@ double hogwild_in_flight_sh(const GraphDev &g, const TileCfg &c, unsigned long l
     unsigned grid = 0;
 #define LH_PLAN_H(L, C)                                                                                  \
     if (c.lps == L && c.upl == C) {                                                                      \
-        if (!SH && g.K <= 5 && L * C == g.nunits)                                                        \
+        if (!SH && g.K == 5 && L * C == g.nunits)                                                        \
             return plan_launch(k_hogwild<TT, L, C, 5, ORD, false, true>, L, g, c, count, num_cu, &grid);   \
         return plan_launch(g.K <= 5 ? k_hogwild<TT, L, C, 5, ORD, SH> : k_hogwild<TT, L, C, 8, ORD, SH>, L, g, c, \
                            count, num_cu, &grid);                                                        \
@@ -206,7 +206,7 @@ hipError_t launch_hogwild_sh(const GraphDev &g, const TileCfg &c, unsigned long 
     const bool k5 = g.K <= 5;
 #define LH_LAUNCH_H(L, C)                                                                        \
     if (c.lps == L && c.upl == C) {                                                              \
-        if (!SH && k5 && L * C == g.nunits)                                                      \
+        if (!SH && g.K == 5 && L * C == g.nunits)                                                \
             return launch_one(k_hogwild<TT, L, C, 5, ORD, false, true>, L, g, c, first, end, num_cu, sc, s); \
         if (k5) return launch_one(k_hogwild<TT, L, C, 5, ORD, SH>, L, g, c, first, end, num_cu, sc, s); \
         return launch_one(k_hogwild<TT, L, C, 8, ORD, SH>, L, g, c, first, end, num_cu, sc, s);        \

@@ -207,8 +207,9 @@ __device__ __forceinline__ void store_coherent(uint32_t *p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// FULL: the shape covers the row exactly (LPS * UPL == units per row), so no access needs
-// a bounds mask and the loads and stores of a sample are straight-line code.
+// FULL: the shape covers the row exactly (LPS * UPL == units per row) and the sample has
+// exactly KMAX negatives, so no access needs a bounds mask or a slot test and the loads and
+// stores of a sample are straight-line code.
 template <typename TT, int LPS, int UPL, bool FULL>
 __device__ __forceinline__ void load_row(const TT *row, int nunits, int gl, uint32_t (&o)[UPL])
 {
@@ -272,7 +273,7 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
     load_row_raw<TT, LPS, UPL, SH, FULL>(g, tA, u, gl, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
-        if (j <= K) {
+        if (FULL || j <= K) {
             load_row_raw<TT, LPS, UPL, SH, FULL>(g, tB, ids[j], gl, r.b[j], bh[j]);
         } else {
 #pragma unroll
@@ -282,7 +283,7 @@ __device__ __forceinline__ void load_rows(Rows<TT, UPL, KMAX> &r, const GraphDev
     pack_shadow_row<TT, UPL, SH>(u, r.a, ah);
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j)
-        if (j <= K) pack_shadow_row<TT, UPL, SH>(ids[j], r.b[j], bh[j]);
+        if (FULL || j <= K) pack_shadow_row<TT, UPL, SH>(ids[j], r.b[j], bh[j]);
 }
 
 // Stochastic-rounding bits of unit un of a row: a Weyl step from the row's seed, one
@@ -315,8 +316,8 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
 {
     constexpr int EPU = Elem<TT>::EPU;
     const int nunits = g.nunits;
-    if constexpr (EPU == 2) {
-        if (SH && id < 0) {
+    if constexpr (EPU == 2 && SH) {
+        if (id < 0) {
             float *sw = g.shadow[t] + (long long)(~id) * g.d;
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
@@ -330,46 +331,51 @@ __device__ __forceinline__ void write_row(const GraphDev &g, int t, int id, int 
             }
             return;
         }
-        if (hot) {
-            uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
-            // (a dry run, step size scaled to zero, issues every atomic, so that a timing run
-            // pays for the hot set as training does)
-            const bool all = g.eta_scale == 0.0f;
+    }
+    // The word of each unit, computed without branches: the new value (binary32), or its
+    // stochastic rounding (bfloat16), for a store; the increment (binary32), or
+    // SR(old + inc) - old rounded to nearest (bfloat16), for an atomic.  Then exactly one
+    // memory instruction per unit, a store or an atomic.
+    uint32_t word[UPL];
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) {
-                const int un = k * LPS + gl;
-                if (FULL || un < nunits) {
-                    const float o0 = val<TT>(old[k], 0), o1 = val<TT>(old[k], 1);
-                    const uint32_t nv = bf16x2_sr(o0 + inc[k][0], o1 + inc[k][1], sr_bits(rseed, un));
-                    const uint32_t p = bf16x2_rne(val<TT>(nv, 0) - o0, val<TT>(nv, 1) - o1);
-                    if ((p & 0x7fff7fffu) != 0u || all)
-                        __builtin_amdgcn_global_atomic_fadd_v2bf16(
-                            (short2_t __attribute__((address_space(1))) *)(w + un),
-                            __builtin_bit_cast(short2_t, p));
-                }
-            }
-            return;
+    for (int k = 0; k < UPL; ++k) {
+        const int un = k * LPS + gl;
+        if constexpr (EPU == 2) {
+            const float o0 = val<TT>(old[k], 0), o1 = val<TT>(old[k], 1);
+            const uint32_t nv = bf16x2_sr(o0 + inc[k][0], o1 + inc[k][1], sr_bits(rseed, un));
+            const uint32_t p = bf16x2_rne(val<TT>(nv, 0) - o0, val<TT>(nv, 1) - o1);
+            word[k] = hot ? p : nv;
+        } else {
+            const float o = val<TT>(old[k], 0);
+            word[k] = __float_as_uint(hot ? inc[k][0] : o + inc[k][0]);
         }
     }
     uint32_t *w = reinterpret_cast<uint32_t *>((TT *)g.tab[t] + (long long)id * g.d);
-    if (!hot) {
+    // Units whose bfloat16 increments are both zero are skipped, except in a dry run (step
+    // size scaled to zero), so that a timing run pays for the hot set as training does, and
+    // in FULL kernels, whose rows each take exactly one memory instruction per unit so that
+    // the count of memory operations after each load is known to the compiler.
+    const bool all = FULL || g.eta_scale == 0.0f;
+    if (hot) {
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const int un = k * LPS + gl;
             if (FULL || un < nunits) {
-                float x[EPU];
-#pragma unroll
-                for (int e = 0; e < EPU; ++e) x[e] = val<TT>(old[k], e) + inc[k][e];
-                uint32_t rnd = 0u;
-                if constexpr (EPU == 2) rnd = sr_bits(rseed, un);
-                store_coherent(w + un, f32_to_unit<TT>(x, rnd));
+                if constexpr (EPU == 2) {
+                    if (all || (word[k] & 0x7fff7fffu) != 0u)
+                        __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                            (short2_t __attribute__((address_space(1))) *)(w + un),
+                            __builtin_bit_cast(short2_t, word[k]));
+                } else {
+                    atomicAdd(reinterpret_cast<float *>(w) + un, __uint_as_float(word[k]));
+                }
             }
         }
     } else {
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
             const int un = k * LPS + gl;
-            if (FULL || un < nunits) atomicAdd(reinterpret_cast<float *>(w) + un, inc[k][0]);
+            if (FULL || un < nunits) store_coherent(w + un, word[k]);
         }
     }
 }
@@ -416,7 +422,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-xs));
         const float gg = gl == 0 ? eta * (1.0f - sg) : -eta * g.alpha * sg;
 #pragma unroll
-        for (int j = 0; j <= KMAX; ++j) gj[j] = j <= K ? group_lane<LPS>(gg, j) : 0.f;
+        for (int j = 0; j <= KMAX; ++j) gj[j] = (FULL || j <= K) ? group_lane<LPS>(gg, j) : 0.f;
     } else {
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
@@ -494,7 +500,7 @@ __device__ __forceinline__ void sgd_order(const GraphDev &g, int u, const int (&
         // context rows
 #pragma unroll
         for (int j = 0; j <= KMAX; ++j) {
-            if (j > K) break;
+            if (!FULL && j > K) break;
             float inc[UPL][EPU];
 #pragma unroll
             for (int k = 0; k < UPL; ++k)
