@@ -198,34 +198,94 @@ def median(xs):
     return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
 
 
-def cpu_baseline(cfg, g, seed, target_s=15.0):
-    """The oracle's binary32 Hogwild mode on the host cores, on a bounded prefix of the
-    same sample stream."""
-    import numpy as np
+def _timed_chunks(run, first, count, chunks=5, say=None):
+    """Run samples [first, first + count) as `chunks` consecutive equal parts; return each
+    part's rate (samples/s)."""
+    rates = []
+    per = count // chunks
+    for i in range(chunks):
+        t = time.perf_counter()
+        run(first + i * per, per)
+        rates.append(per / (time.perf_counter() - t))
+        if say:
+            say(f"part {i + 1} of {chunks}: {rates[-1]:.4g} samples/s")
+    return rates
+
+
+def cpu_baseline(cfg, g, seed, target_s=15.0, chunks=5, label="same workload"):
+    """The oracle's binary32 Hogwild mode on every host core this process may use, over a
+    bounded prefix of the same sample stream, timed as `chunks` consecutive parts: the
+    reported value is the median part's rate."""
     import oracle
     threads, cores, cap = host_threads()
     t0 = time.time()
-    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+
+    def say(msg):
+        log(f"[bench] oracle: {msg} ({time.time() - t0:.1f}s)")
+
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w, progress=say)
     d, K, orders, T = cfg["d"], cfg["K"], cfg["orders"], int(cfg["T"])
-    U = oracle.init_table(0, g.n, d, seed, 0) if orders & 2 else None
-    C = oracle.init_table(1, g.n, d, seed, 0) if orders & 2 else None
-    U1 = oracle.init_table(2, g.n, d, seed, 0) if orders & 1 else None
-    log(f"[bench] oracle tables ready in {time.time() - t0:.1f}s, {threads} threads")
+    U = C = U1 = None
+    if orders & 2:
+        U = oracle.init_table(0, g.n, d, seed, 0)
+        say("U initialised")
+        C = oracle.init_table(1, g.n, d, seed, 0)
+        say("C initialised")
+    if orders & 1:
+        U1 = oracle.init_table(2, g.n, d, seed, 0)
+        say("U1 initialised")
+    prep_s = time.time() - t0
+    log(f"[bench] oracle tables ready in {prep_s:.1f}s, {threads} threads")
+
+    def run(first, count):
+        oracle.train_hogwild_f32(tb, U, C, U1, d, K, orders, T, seed, 0, first, count, threads)
+
     probe = 200_000
     t1 = time.perf_counter()
-    oracle.train_hogwild_f32(tb, U, C, U1, d, K, orders, T, seed, 0, 0, probe, threads)
+    run(0, probe)
     rate = probe / (time.perf_counter() - t1)
-    count = int(min(max(rate * target_s, probe), T - probe))
-    t2 = time.perf_counter()
-    oracle.train_hogwild_f32(tb, U, C, U1, d, K, orders, T, seed, 0, probe, count, threads)
-    dt = time.perf_counter() - t2
-    del U, C, U1
-    return {"value": count / dt, "unit": "edge samples/s", "cores": threads, "kind": "oracle",
-            "affinity_cores": cores, "thread_cap": cap or None,
-            "sample": f"samples [{probe}, {probe + count}) of the same workload and seed "
-                      f"({count} samples, {dt:.1f} s), binary32 lock-free mode of the oracle, "
-                      f"{threads} OpenMP threads of {cores} in the affinity mask; alias build and init "
-                      "excluded"}
+    count = int(min(max(rate * target_s, chunks * probe), T - probe))
+    rates = _timed_chunks(run, probe, count, chunks, say)
+    del U, C, U1, tb
+    per = count // chunks
+    return {"value": median(rates), "unit": "edge samples/s", "cores": threads, "kind": "oracle",
+            "affinity_cores": cores, "thread_cap": cap or None, "chunk_rates": rates,
+            "table_prep_s": prep_s,
+            "sample": f"samples [{probe}, {probe + chunks * per}) of the {label} and seed, timed as "
+                      f"{chunks} consecutive parts of {per} samples (median part reported), binary32 "
+                      f"lock-free mode of the oracle, {threads} OpenMP threads of {cores} in the "
+                      "affinity mask; alias build and init excluded"}
+
+
+def oracle_seq_timings(g2, cfg2, seed2, c2_prefix=1_000_000, chunks=5):
+    """The oracle's single-thread binary64 SEQ mode (the one the stored AUC references come
+    from): C1 in full, `chunks` times, and a prefix of C2 as `chunks` consecutive parts.
+    Median rates (samples/s)."""
+    import oracle
+    from synth import CONFIGS, config_graph
+    out = {}
+    cfg1 = CONFIGS["C1"]
+    g1, _, _, _ = config_graph("C1")
+    t1 = oracle.Tables(g1.n, g1.src, g1.dst, g1.w)
+    T1 = int(cfg1["T"])
+    rates = []
+    for _ in range(chunks):
+        m = oracle.Model(t1, d=cfg1["d"], K=cfg1["K"], orders=cfg1["orders"], T=T1, seed=cfg1["seed"],
+                         eta0=cfg1["eta0"])
+        t = time.perf_counter()
+        m.train(0, T1, "seq")
+        rates.append(T1 / (time.perf_counter() - t))
+    out["C1"] = {"value": median(rates), "runs": rates, "threads": 1,
+                 "sample": f"all T = {T1} samples, {chunks} runs from the initial tables"}
+    t2 = oracle.Tables(g2.n, g2.src, g2.dst, g2.w)
+    m = oracle.Model(t2, d=cfg2["d"], K=cfg2["K"], orders=cfg2["orders"], T=int(cfg2["T"]), seed=seed2,
+                     eta0=cfg2["eta0"])
+    rates = _timed_chunks(lambda f, c: m.train(f, c, "seq"), 0, c2_prefix, chunks)
+    out["C2"] = {"value": median(rates), "runs": rates, "threads": 1,
+                 "sample": f"samples [0, {c2_prefix}) as {chunks} consecutive parts"}
+    out["unit"] = "edge samples/s"
+    out["kind"] = "oracle binary64 SEQ"
+    return out
 
 
 def c3_embedding_error(cfg, g, seed, count=1 << 20, batch=65536):
@@ -344,6 +404,11 @@ def bench_large(args):
         src, dst, w = rmat_graph_gpu(cfg["scale"], cfg["n"], cfg["m_unique"], cfg["seed"])
     torch.cuda.synchronize()
     log(f"[bench] {name} graph generated on the GPU in {time.time() - t0:.1f}s")
+    host_graph = None
+    if args.cpu_slice:
+        from synth.graphs import Graph
+        host_graph = Graph(n=cfg["n"], src=src.cpu().numpy(), dst=dst.cpu().numpy(), w=w.cpu().numpy())
+        log(f"[bench] {name} graph copied to the host ({time.time() - t0:.1f}s)")
     T = int(cfg["T"]) if args.c5_samples is None else int(args.c5_samples)
     tr = Trainer(cfg["n"], src, dst, w, d=cfg["d"], K=cfg["K"], orders=cfg["orders"], dtype="bf16",
                  seed=cfg["seed"], total_samples=T, build=False, init=False, hot_shadow=args.hot_shadow)
@@ -359,18 +424,29 @@ def bench_large(args):
     achieved = bps * T / (ms * 1e-3) / 1e9
     graph = ("uniform random endpoints (control), unit weights" if name == "C5U"
              else "directed R-MAT scale 26, lognormal weights")
-    return {
+    kcfg = tr.kernel_config()
+    cpu = None
+    if host_graph is not None:
+        tr.close()
+        del tr
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(dict(cfg, T=T), host_graph, cfg["seed"], label=f"{name} workload")
+        log(f"[bench] cpu baseline {cpu['value']:.3e} samples/s")
+    out = {
         "metric": f"edge samples/sec at d=128,K=5 ({name}, bf16)", "value": T / (ms * 1e-3),
         "unit": "edge samples/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "table_dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"{name}: {graph}, 67108864 nodes, 2^30 arcs, d=128, K=5, second order, "
                                "bf16 tables", "T": T,
-                   "kernel_config": tr.kernel_config(), "alias_build_s": build_s, "hot_shadow": args.hot_shadow},
+                   "kernel_config": kcfg, "alias_build_s": build_s, "hot_shadow": args.hot_shadow},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_hogwild (bf16, order 2)",
                      "bytes_per_sample": bps},
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
 
 
 def main():
@@ -381,6 +457,10 @@ def main():
     ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5", "C5U"])
     ap.add_argument("--c5-samples", type=float, default=None, help="override T for C5 and C5U")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-slice", action="store_true",
+                    help="C5 and C5U: also time the oracle's binary32 lock-free mode on the host over a "
+                         "bounded prefix (builds the oracle's tables for 2^30 arcs: minutes, ~130 GB of "
+                         "host memory)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
@@ -509,6 +589,8 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cfg, g, seed)
         log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.3e} samples/s")
+        result["cpu_baseline"]["seq_binary64"] = oracle_seq_timings(g, cfg, seed)
+        log(f"[bench] oracle SEQ timings {result['cpu_baseline']['seq_binary64']}")
 
     print(json.dumps(result), flush=True)
 

@@ -168,15 +168,21 @@ def apply_tuple(A, B, u: int, ids, eta: float, lam: float = 0.0, alpha: float = 
 class Tables:
     """Edge table over arcs (weights w) and negative table over nodes (Eq. (1))."""
 
-    def __init__(self, n: int, src, dst, w):
+    def __init__(self, n: int, src, dst, w, progress=None):
+        """``progress``, if given, is called with a short message after each step (large
+        graphs take minutes)."""
+        say = progress or (lambda msg: None)
         self.n = int(n)
         self.src = _c(src, np.int32)
         self.dst = _c(dst, np.int32)
         self.w = _c(w, np.float32)
         self.m = int(self.src.size)
         self.deg = out_degree(self.src, self.n)
+        say("out-degrees")
         self.ethr, self.ealias = alias_build(self.w.astype(np.float64))
+        say("edge alias table")
         self.nthr, self.nalias = alias_build(neg_weights(self.deg))
+        say("negative alias table")
 
 
 def sample(t: Tables, seed: int, graph_id: int, K: int, first: int, count: int):

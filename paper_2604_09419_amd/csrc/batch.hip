@@ -118,8 +118,8 @@ extern "C" lh_status lh_tune(lh_handle *h, uint64_t probe, const char *cache_pat
     const int nu = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;
     GraphDev g = graph_dev(h);
     // Dry run: the step size is scaled to zero, so every row is written back unchanged,
-    // and hot rows still issue their atomics (bfloat16 ones too, whose zero increments a
-    // training run skips), so the timing includes what the hot set costs.
+    // and hot rows still issue their atomics (bfloat16 ones too, whose zero increments the
+    // masked training kernels skip), so the timing includes what the hot set costs.
     g.eta_scale = 0.0f;
     const int bpc_opts[] = {1, 2, 3, 4, 8, 16};
     // Candidate shapes: the compiled (lanes, units) that cover a row with the fewest
