@@ -80,6 +80,18 @@ def lib():
         L.or_draw_item.argtypes = [P, P, i64, u64, u64]
         L.or_draw_item.restype = i64
         L.or_apply_tuple.argtypes = [P, P, i32, i32, i32, P, f64, f64, f64]
+        if hasattr(L, "or_walk_csr"):
+            L.or_walk_csr.argtypes = [i64, i64, P, P, P, P, P, P]
+            L.or_walk_csr.restype = i32
+            L.or_walk_alias.argtypes = [i64, P, P, P, P]
+            L.or_walk_pairs.argtypes = [i64, i64, P, P, P, P, P, P, P, P, u64, u32, i32, i32, i64,
+                                        u64, u64, P, P]
+            L.or_walk_pairs.restype = i32
+            L.or_walk_vertices.argtypes = [i64, i64, P, P, P, P, P, P, P, P, u64, u32, i32, u64, u64, P]
+            L.or_walk_vertices.restype = i32
+            L.or_train_walk.argtypes = [P, P, i64, i64, P, P, P, P, P, P, P, P, i32, i32, i64, u64, u32,
+                                        i32, i32, i32, f64, f64, f64, u64, P, P, P, u64, u64, i32, u64]
+            L.or_train_walk.restype = i32
         _lib = L
     return _lib
 
@@ -185,6 +197,53 @@ class Tables:
         say("negative alias table")
 
 
+class WalkGraph:
+    """The random-walk pair source (Sec. IV-B, Algorithms 2-3) over the undirected graph of
+    ``tables``' arcs: CSR rows of the neighbourhoods N(x) (entry e < m is arc e forwards,
+    m + e arc e backwards, in entry order within a row), the per-row alias tables of
+    discrete(N(x)), and the walk shape: L vertices per walk, window W (pairs of walk
+    positions less than W apart), Bw walks per batch (the sample order interleaves a
+    batch's walks)."""
+
+    def __init__(self, tables: "Tables", L: int = 100, W: int = 2, Bw: int = 1 << 17):
+        t = tables
+        self.t, self.L, self.W, self.Bw = t, int(L), int(W), int(Bw)
+        self.off = np.zeros(t.n + 1, dtype=np.int64)
+        self.nbr = np.zeros(2 * t.m, dtype=np.int32)
+        self.wt = np.zeros(2 * t.m, dtype=np.float64)
+        if lib().or_walk_csr(t.n, t.m, _p(t.src), _p(t.dst), _p(t.w), _p(self.off), _p(self.nbr),
+                             _p(self.wt)) != 0:
+            raise ValueError("or_walk_csr rejected its arguments")
+        self.thr = np.zeros(2 * t.m, dtype=np.uint64)
+        self.alias = np.zeros(2 * t.m, dtype=np.int32)
+        lib().or_walk_alias(t.n, _p(self.off), _p(self.wt), _p(self.thr), _p(self.alias))
+
+    @property
+    def pairs_per_walk(self) -> int:
+        return sum(self.L - dl for dl in range(1, self.W))
+
+    def _args(self):
+        t = self.t
+        return (t.n, t.m, _p(t.src), _p(t.dst), _p(t.ethr), _p(t.ealias), _p(self.off), _p(self.nbr),
+                _p(self.thr), _p(self.alias))
+
+    def pairs(self, seed: int, graph_id: int, first: int, count: int):
+        """(u, v) of samples [first, first + count)."""
+        u = np.zeros(count, dtype=np.int32)
+        v = np.zeros(count, dtype=np.int32)
+        if lib().or_walk_pairs(*self._args(), seed, graph_id, self.L, self.W, self.Bw, first, count,
+                               _p(u), _p(v)) != 0:
+            raise ValueError("or_walk_pairs rejected its arguments")
+        return u, v
+
+    def walks(self, seed: int, graph_id: int, k0: int, nwalks: int) -> np.ndarray:
+        """Vertices of walks k0 .. k0 + nwalks - 1, [nwalks, L]."""
+        out = np.zeros((nwalks, self.L), dtype=np.int32)
+        if lib().or_walk_vertices(*self._args(), seed, graph_id, self.L, k0, nwalks, _p(out)) != 0:
+            raise ValueError("or_walk_vertices rejected its arguments")
+        return out
+
+
 def sample(t: Tables, seed: int, graph_id: int, K: int, first: int, count: int):
     """Sampled tuples (u, v, neg[count, K]) for sample indices [first, first+count)."""
     u = np.zeros(count, dtype=np.int32)
@@ -257,9 +316,24 @@ class Model:
                 if X is not None:
                     lib().or_bf16_rne(_p(X), X.size)
 
-    def train(self, first: int, count: int, mode: str = "seq", batch: int = 0):
-        """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch)."""
+    def train(self, first: int, count: int, mode: str = "seq", batch: int = 0,
+              walks: Optional["WalkGraph"] = None):
+        """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch).  ``walks``:
+        positive pairs from that random-walk source instead of arc draws."""
         t = self.t
+        if walks is not None:
+            if self.storage != "binary64":
+                raise ValueError("walk pairs are modelled with binary64 storage")
+            wg = walks
+            rc = lib().or_train_walk(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                                     _p(t.nthr), _p(t.nalias), _p(wg.off), _p(wg.nbr), _p(wg.thr),
+                                     _p(wg.alias), wg.L, wg.W, wg.Bw, self.seed, self.graph_id, self.d,
+                                     self.K, self.orders, self.eta0, self.lam, self.alpha, self.T,
+                                     _p(self.U), _p(self.C), _p(self.U1), first, count,
+                                     0 if mode == "seq" else 1, batch)
+            if rc != 0:
+                raise ValueError("or_train_walk rejected its arguments")
+            return
         if self.storage == "bf16":
             if mode != "seq":
                 raise ValueError("bfloat16 storage is modelled in SEQ mode only")

@@ -17,6 +17,8 @@
  *     against the copy fetched at the start of the batch (the SNAPSHOT mode below).
  *   - Algorithm 3 (GeneratePairs), root selection: a positive pair is an edge drawn from
  *     the weight-normalised edge distribution.
+ *   - Algorithms 2-3 (RandomWalk, GeneratePairs), Sec. IV-B: positive pairs from random
+ *     walks rooted at such an edge (the walk pair source below).
  *   - Sec. V-A (NOMAD hyperparameters): single-precision SGD, eta = 0.025.
  *
  * Floating point: everything here is IEEE binary64 except the Hogwild timing mode,
@@ -272,15 +274,24 @@ typedef struct {
     const uint64_t *nthr; const int32_t *nalias;
     uint64_t seed; uint32_t graph_id;
     int K;
+    /* Positive pairs from random walks instead of arc draws: the pair of sample s is     */
+    /* (pu[s - pfirst], pv[s - pfirst]); NULL: slot 0 draws an arc.                       */
+    const int32_t *pu, *pv;
+    uint64_t pfirst;
 } or_graph;
 
 static void draw_tuple(const or_graph *g, uint64_t s, int32_t *u, int32_t *v, int32_t *neg)
 {
     uint64_t ctr[4] = {s, 0, 0, 0}, x[4];
-    or_philox4x64_10(g->seed, (uint64_t)g->graph_id, ctr, x);
-    int64_t a = draw(g->ethr, g->ealias, g->m, x[0], x[1]);
-    *u = g->src[a];
-    *v = g->dst[a];
+    if (g->pu) {
+        *u = g->pu[s - g->pfirst];
+        *v = g->pv[s - g->pfirst];
+    } else {
+        or_philox4x64_10(g->seed, (uint64_t)g->graph_id, ctr, x);
+        int64_t a = draw(g->ethr, g->ealias, g->m, x[0], x[1]);
+        *u = g->src[a];
+        *v = g->dst[a];
+    }
     for (int j = 1; j <= g->K; j++) {
         ctr[1] = (uint64_t)j;
         or_philox4x64_10(g->seed, (uint64_t)g->graph_id, ctr, x);
@@ -294,7 +305,7 @@ void or_sample(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                uint64_t seed, uint32_t graph_id, int K,
                uint64_t first, uint64_t count, int32_t *u, int32_t *v, int32_t *neg)
 {
-    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K};
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
     for (uint64_t i = 0; i < count; i++)
         draw_tuple(&g, first + i, &u[i], &v[i], &neg[i * (uint64_t)K]);
 }
@@ -390,20 +401,15 @@ void or_apply_tuple(double *A, double *B, int d, int K, int32_t u, const int32_t
     free(dA); free(dB);
 }
 
-int or_train(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
-             const uint64_t *ethr, const int32_t *ealias,
-             const uint64_t *nthr, const int32_t *nalias,
-             uint64_t seed, uint32_t graph_id,
-             int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
-             double *U, double *C, double *U1,
-             uint64_t first, uint64_t count, int mode, uint64_t batch)
+static int train_range(const or_graph *gp, const or_hyper *hp, double *U, double *C, double *U1,
+                       uint64_t first, uint64_t count, int mode, uint64_t batch)
 {
-    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
-    if ((orders & 2) && (!U || !C)) return 1;
-    if ((orders & 1) && !U1) return 1;
-    if (mode == 1 && batch == 0) return 1;
-    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K};
-    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    const or_graph g = *gp;
+    const or_hyper h = *hp;
+    const int64_t n = g.n;
+    const int d = h.d, K = h.K, orders = h.orders;
+    const double eta0 = h.eta0;
+    const uint64_t T = h.T;
     int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(K + 1));
     double *dA = (double *)malloc(sizeof(double) * (size_t)d);
     double *dB = (double *)malloc(sizeof(double) * (size_t)d * (size_t)(K + 1));
@@ -473,6 +479,218 @@ int or_train(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
     }
     free(ids); free(dA); free(dB);
     return 0;
+}
+
+int or_train(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+             const uint64_t *ethr, const int32_t *ealias,
+             const uint64_t *nthr, const int32_t *nalias,
+             uint64_t seed, uint32_t graph_id,
+             int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+             double *U, double *C, double *U1,
+             uint64_t first, uint64_t count, int mode, uint64_t batch)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    if (mode == 1 && batch == 0) return 1;
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    return train_range(&g, &h, U, C, U1, first, count, mode, batch);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Random-walk positive pairs (Sec. IV-B: Algorithm 2, RandomWalk, and          */
+/* Algorithm 3, GeneratePairs) on one process, where every vertex is local, so  */
+/* the walk never stops at a remote vertex (the "Local" variant over the whole  */
+/* graph).                                                                     */
+/*                                                                             */
+/* Walk graph: the undirected graph of the arcs, as the paper walks undirected */
+/* graphs.  Entry e < m is arc e forwards (tail src[e], head dst[e]); entry     */
+/* m + e is arc e backwards (tail dst[e], head src[e]); both weigh w[e].  The   */
+/* neighbourhood N(x) lists the entries with tail x in increasing entry index:  */
+/* CSR rows off[x] .. off[x+1], heads nbr[], weights wt[].                      */
+/*                                                                             */
+/* discrete(N(x)) is an alias table over the row's weights (or_alias_build on   */
+/* the row, items numbered from 0 within the row).  A row whose weights sum to  */
+/* zero gets prob 1 and itself everywhere; no walk reaches it, since every     */
+/* step leaves along an entry of positive weight and the reverse entry then    */
+/* has that weight too.                                                        */
+/*                                                                             */
+/* Walk k, vertices w_0 .. w_{L-1} (L = walk length: Algorithm 2 counts the    */
+/* visited vertices, root pair included, up to it), Philox4x64-10 with key      */
+/* (seed, 5 * 2^32 | graph_id):                                                 */
+/*   block (k, 0, 0, 0) draws the root arc a from the edge table (Algorithm 3,  */
+/*   the weight-normalised edge distribution): w_0 = src[a], w_1 = dst[a];      */
+/*   block (k, t, 0, 0), t = 1 .. L-2, draws w_{t+1} from discrete(N(w_t)).     */
+/* Pairs of a walk: (w_i, w_{i+delta}) for delta = 1 .. W-1 (window W; W = 2   */
+/* gives the consecutive pairs Algorithm 2 collects into its path), numbered    */
+/* p = sum_{delta' < delta} (L - delta') + i; P pairs per walk.                 */
+/* Sample order (Algorithm 3 shuffles the pairs of a batch): walks come in      */
+/* batches of Bw, and sample s = b Bw P + p Bw + j is pair p of walk b Bw + j,  */
+/* so consecutive samples come from different walks.                            */
+/* ------------------------------------------------------------------------- */
+#define OR_WALK_TAG 5ULL
+
+int or_walk_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+                int64_t *off, int32_t *nbr, double *wt)
+{
+    if (n < 1 || m < 0) return 1;
+    int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t x = 0; x <= n; x++) off[x] = 0;
+    for (int64_t e = 0; e < m; e++) { off[src[e] + 1]++; off[dst[e] + 1]++; }
+    for (int64_t x = 0; x < n; x++) off[x + 1] += off[x];
+    for (int64_t e = 0; e < 2 * m; e++) {
+        int64_t a = e < m ? e : e - m;
+        int32_t tail = e < m ? src[a] : dst[a], head = e < m ? dst[a] : src[a];
+        int64_t pos = off[tail] + fill[tail]++;
+        nbr[pos] = head;
+        wt[pos] = (double)w[a];
+    }
+    free(fill);
+    return 0;
+}
+
+void or_walk_alias(int64_t n, const int64_t *off, const double *wt, uint64_t *thr, int32_t *alias)
+{
+    for (int64_t x = 0; x < n; x++) {
+        int64_t lo = off[x], len = off[x + 1] - off[x];
+        if (len == 0) continue;
+        if (or_alias_build(wt + lo, len, thr + lo, alias + lo) != 0) {
+            for (int64_t i = 0; i < len; i++) { thr[lo + i] = UINT64_MAX; alias[lo + i] = (int32_t)i; }
+        }
+    }
+}
+
+typedef struct {
+    int64_t n, m;
+    const int32_t *src, *dst;
+    const uint64_t *ethr; const int32_t *ealias;
+    const int64_t *off; const int32_t *nbr;
+    const uint64_t *wthr; const int32_t *walias;
+    uint64_t seed; uint32_t graph_id;
+    int L, W;
+    int64_t Bw;
+} or_walker;
+
+static void walk_vertices(const or_walker *wk, uint64_t k, int32_t *vert)
+{
+    uint64_t key1 = (OR_WALK_TAG << 32) | (uint64_t)wk->graph_id, ctr[4] = {k, 0, 0, 0}, x[4];
+    or_philox4x64_10(wk->seed, key1, ctr, x);
+    int64_t a = draw(wk->ethr, wk->ealias, wk->m, x[0], x[1]);
+    vert[0] = wk->src[a];
+    vert[1] = wk->dst[a];
+    for (int t = 1; t + 1 < wk->L; t++) {
+        ctr[1] = (uint64_t)t;
+        or_philox4x64_10(wk->seed, key1, ctr, x);
+        int64_t lo = wk->off[vert[t]], len = wk->off[vert[t] + 1] - lo;
+        int64_t item = draw(wk->wthr + lo, wk->walias + lo, len, x[0], x[1]);
+        vert[t + 1] = wk->nbr[lo + item];
+    }
+}
+
+static int64_t walk_pairs_per_walk(int L, int W)
+{
+    int64_t P = 0;
+    for (int delta = 1; delta < W; delta++) P += L - delta;
+    return P;
+}
+
+/* The pair (first, second position) with number p of a walk. */
+static void walk_pair_positions(int L, int W, int64_t p, int *i, int *j)
+{
+    int delta = 1;
+    while (delta < W && p >= L - delta) { p -= L - delta; delta++; }
+    *i = (int)p;
+    *j = (int)p + delta;
+}
+
+static int walker_ok(const or_walker *wk)
+{
+    return wk->L >= 2 && wk->W >= 2 && wk->W <= wk->L && wk->Bw >= 1 && wk->m >= 1;
+}
+
+/* The positive pairs of samples [first, first + count). */
+int or_walk_pairs(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                  uint64_t seed, uint32_t graph_id, int L, int W, int64_t Bw,
+                  uint64_t first, uint64_t count, int32_t *u, int32_t *v)
+{
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
+    if (!walker_ok(&wk)) return 1;
+    const uint64_t P = (uint64_t)walk_pairs_per_walk(L, W), per = (uint64_t)Bw * P;
+    int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+    uint64_t have = UINT64_MAX;
+    for (uint64_t i = 0; i < count; i++) {
+        uint64_t s = first + i, b = s / per, r = s % per, p = r / (uint64_t)Bw, j = r % (uint64_t)Bw;
+        uint64_t k = b * (uint64_t)Bw + j;
+        if (k != have) { walk_vertices(&wk, k, vert); have = k; }
+        int a, c;
+        walk_pair_positions(L, W, (int64_t)p, &a, &c);
+        u[i] = vert[a];
+        v[i] = vert[c];
+    }
+    free(vert);
+    return 0;
+}
+
+/* Whole walks k0 .. k0 + nwalks - 1: vertex t of walk k into vert[(k - k0) L + t]. */
+int or_walk_vertices(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     const uint64_t *ethr, const int32_t *ealias,
+                     const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                     uint64_t seed, uint32_t graph_id, int L, uint64_t k0, uint64_t nwalks, int32_t *vert)
+{
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, 2, 1};
+    if (!walker_ok(&wk)) return 1;
+    for (uint64_t k = 0; k < nwalks; k++) walk_vertices(&wk, k0 + k, vert + k * (uint64_t)L);
+    return 0;
+}
+
+/* Training (or_train) with the positive pairs of the walks: Algorithm 3 generates the
+ * pairs of each walk batch, then Algorithm 1 trains them in sample order.  SNAPSHOT needs
+ * every batch [bB, (b+1)B) inside one walk batch: Bw P a multiple of B. */
+int or_train_walk(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const uint64_t *nthr, const int32_t *nalias,
+                  const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                  int L, int W, int64_t Bw,
+                  uint64_t seed, uint32_t graph_id,
+                  int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+                  double *U, double *C, double *U1,
+                  uint64_t first, uint64_t count, int mode, uint64_t batch)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    if (mode == 1 && batch == 0) return 1;
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
+    if (!walker_ok(&wk)) return 1;
+    const uint64_t P = (uint64_t)walk_pairs_per_walk(L, W), per = (uint64_t)Bw * P;
+    if (mode == 1 && per % batch != 0) return 1;
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    int32_t *pv = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+    const uint64_t end = first + count;
+    int rc = 0;
+    for (uint64_t s = first; s < end && rc == 0;) {
+        uint64_t b = s / per, b0 = b * per, b1 = b0 + per;
+        for (uint64_t j = 0; j < (uint64_t)Bw; j++) {
+            walk_vertices(&wk, b * (uint64_t)Bw + j, vert);
+            for (uint64_t p = 0; p < P; p++) {
+                int a, c;
+                walk_pair_positions(L, W, (int64_t)p, &a, &c);
+                pu[p * (uint64_t)Bw + j] = vert[a];
+                pv[p * (uint64_t)Bw + j] = vert[c];
+            }
+        }
+        or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, pu, pv, b0};
+        uint64_t stop = b1 < end ? b1 : end;
+        rc = train_range(&g, &h, U, C, U1, s, stop - s, mode, batch);
+        s = stop;
+    }
+    free(pu); free(pv); free(vert);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -552,7 +770,7 @@ int or_train_bf16(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
     if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
     if ((orders & 2) && (!U || !C)) return 1;
     if ((orders & 1) && !U1) return 1;
-    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K};
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
     or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
     int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(K + 1));
     double *dA = (double *)malloc(sizeof(double) * (size_t)d);
@@ -592,7 +810,7 @@ int or_train_hogwild_f32(const int32_t *src, const int32_t *dst, int64_t n, int6
     if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
     if ((orders & 2) && (!U || !C)) return 1;
     if ((orders & 1) && !U1) return 1;
-    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K};
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
