@@ -121,8 +121,15 @@ def workload(name: str):
     return cfg, g, hs, hd, neg
 
 
-def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False):
-    """Time `steps` full passes (after `warmup`); return timings and the trainer."""
+# Random-walk pair source of the walk legs (Sec. IV-B): walk length 100 and window 2 (Sec.
+# V-A), walks per batch 1024 (about 10^5 pairs per batch, the paper's batch sizes).
+WALK = dict(walk_length=100, window=2, walks_per_batch=1024)
+
+
+def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False, walks=None):
+    """Time `steps` full passes (after `warmup`); return timings and the trainer.  With
+    `walks`, every pass also builds the walk rows, and training takes its positive pairs
+    from random walks (their generation inside the timed training call)."""
     import torch
     from paper_2604_09419_amd import Trainer
     T = int(cfg["T"])
@@ -138,6 +145,8 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False
         from paper_2604_09419_amd import _lib
         _lib.lh_set_graph(tr.h, tr.n, tr.m, tr.src.data_ptr(), tr.dst.data_ptr(), tr.w.data_ptr())
         tr.build_alias()
+        if walks:
+            tr.build_walks(**walks)
         tr.init_embeddings()
         tr.train_steps(0, T)
         tr.synchronize()
@@ -147,10 +156,39 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False
         if i >= warmup:
             step_ms.append(dt)
             kern_ms.append(km)
-        log(f"[bench] {dtype} step {i} ({'warmup' if i < warmup else 'timed'}): {dt:.1f} ms, "
-            f"train kernel {km:.1f} ms")
+        log(f"[bench] {dtype}{' walks' if walks else ''} step {i} ({'warmup' if i < warmup else 'timed'}): "
+            f"{dt:.1f} ms, train kernel {km:.1f} ms")
     tr.check()
     return tr, step_ms, kern_ms
+
+
+def walk_legs(args, cfg, g, hs, hd, neg, seed, T):
+    """C2 with positive pairs from random walks (WALK), binary32 and bfloat16 tables: step
+    and training-call rates (walk generation included), and held-out AUCs against the
+    oracle's binary64 SEQ run on the same walk pairs."""
+    import torch
+    out = {"pairs": f"random walks {WALK}"}
+    gold_path = os.path.join(GOLDEN, "c2_walk_oracle_auc.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    for dtype in ("fp32", "bf16"):
+        tr, steps_ms, kern_ms = run_gpu_leg(cfg, g, dtype, max(1, args.steps), 1, seed, args.tune_cache,
+                                            hot_shadow=args.hot_shadow, walks=WALK)
+        leg = {"samples_per_s": T / (median(steps_ms) * 1e-3), "train_call_samples_per_s": T / (median(kern_ms) * 1e-3),
+               "kernel_config": tr.kernel_config()}
+        if not args.no_auc:
+            leg["auc"] = held_out_auc(tr, hs, hd, neg, cfg["orders"])
+            if gold:
+                leg["auc_within_0.005_of_oracle"] = all(abs(v - gold["auc_" + k]) <= 0.005
+                                                        for k, v in leg["auc"].items())
+            log(f"[bench] {dtype} walks AUC {leg['auc']}")
+        out[dtype] = leg
+        tr.close()
+        del tr
+        torch.cuda.empty_cache()
+    if gold:
+        out["auc_oracle_binary64"] = {k[4:]: v for k, v in gold.items() if k.startswith("auc_")
+                                      and not k.startswith("auc_init")}
+    return out
 
 
 def held_out_auc(tr, hs, hd, neg, orders):
@@ -464,6 +502,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
+    ap.add_argument("--no-walks", action="store_true", help="skip the random-walk pair legs")
     ap.add_argument("--hot-shadow", action="store_true",
                     help="bfloat16 runs: hot rows accumulate in a binary32 shadow per launch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
@@ -570,6 +609,9 @@ def main():
         tb.close()
         del tb
         torch.cuda.empty_cache()
+
+    if not args.no_walks:
+        result["walks"] = walk_legs(args, cfg, g, hs, hd, neg, seed, T)
 
     gold_path = os.path.join(GOLDEN, "c2_oracle_auc.json")
     if os.path.exists(gold_path):

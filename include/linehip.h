@@ -4,7 +4,8 @@
  *
  * The method (NOMAD, arXiv 2604.09419, Sec. IV "Methods"):
  *   * a positive pair is an arc (u, v) drawn from the weight-normalised edge
- *     distribution (Algorithm 3, root-edge selection);
+ *     distribution (Algorithm 3, root-edge selection), or, after lh_walk_build, a pair
+ *     of a random walk rooted at such an arc (Algorithms 2-3);
  *   * K negatives v- are drawn i.i.d. from q(v) proportional to d(v)^0.75, d the
  *     out-degree (Eq. (1));
  *   * per pair the signed gradient scalar is g = eta (1 - sigma(U[u].C[v])) for the
@@ -272,6 +273,61 @@ LH_API lh_status lh_batch_config(const lh_batch *b, int64_t out[3]);
 /* Samples trained per graph by the last launch/run (uint64[G], host; synchronises). */
 LH_API lh_status lh_batch_done(lh_batch *b, uint64_t *done_per_graph);
 LH_API lh_status lh_batch_destroy(lh_batch *b);
+
+/* ---- Random-walk positive pairs (Sec. IV-B: Algorithm 2, RandomWalk, and Algorithm 3,
+ * GeneratePairs; one GPU, so every vertex is local and no walk stops at a remote one).
+ *
+ * The walk graph is the undirected graph of the arcs: entry e < m is arc e forwards (tail
+ * src[e], head dst[e]), entry m + e arc e backwards; both weigh w[e].  Row x, the
+ * neighbourhood N(x), lists the entries with tail x in increasing entry index, and
+ * discrete(N(x)) is an alias table over the row's weights built like the edge table
+ * (binary64, canonical scans restarting at every row, items numbered within the row).
+ * Walk k draws its root arc from the edge table with Philox4x64-10 key
+ * (seed, 5 * 2^32 | graph_id), counter (k, 0, 0, 0): w_0 = its tail, w_1 = its head;
+ * counter (k, t, 0, 0), t = 1 .. L - 2, draws w_{t+1} from row w_t.  A walk visits
+ * L = walk_length vertices (Algorithm 2 counts visited vertices up to the walk length).
+ * Its pairs are (w_i, w_{i+delta}), delta = 1 .. window - 1 (window 2: the consecutive
+ * pairs Algorithm 2 collects), numbered p = sum_{delta' < delta} (L - delta') + i; P pairs
+ * per walk.  Sample s = b Bw P + p Bw + j (Bw = walks_per_batch) takes pair p of walk
+ * b Bw + j as its positive pair (u, v), so consecutive samples come from different walks
+ * (Algorithm 3 shuffles a batch's pairs); its K negatives are drawn as before.
+ *
+ * lh_walk_size: bytes of device memory for a graph of n nodes and m arcs: *persist (row
+ * offsets, row entries, and a pair buffer of whole walk batches, about 2^24 pairs) and
+ * *scratch (build arrays, free once lh_walk_build has returned).  Host-only.
+ * LH_ERR_INVALID_ARG unless 2 <= walk_length <= 4096, 2 <= window <= min(8, walk_length),
+ * 1 <= walks_per_batch <= 2^24, walks_per_batch * P <= 2^27, m >= 1, 2m < 2^32. */
+LH_API lh_status lh_walk_size(int64_t n, int64_t m, int32_t walk_length, int32_t window, int64_t walks_per_batch,
+                              size_t *persist, size_t *scratch);
+
+/* Build the walk rows of the handle's graph and switch its positive pairs to walks:
+ * afterwards lh_train_steps (both modes) and lh_sample take (u, v) of sample s from the
+ * walks as described above, generating each buffer fill of walks on the handle's stream
+ * when a call first needs it.  persist and scratch: device, 256-byte aligned, at least
+ * lh_walk_size's bytes; the caller owns both and keeps persist alive while the handle
+ * uses the walks.  The graph arrays given to lh_set_graph must still be valid; the edge
+ * table must exist (lh_build_alias).  Synchronises the stream.  LH_ERR_NOT_BUILT before
+ * lh_build_alias; LH_ERR_INVALID_ARG for the ranges of lh_walk_size, or, in SNAPSHOT
+ * mode, when the batch B does not divide walks_per_batch * P (a snapshot batch must lie
+ * within one walk batch); LH_ERR_WORKSPACE_TOO_SMALL.  lh_bind and lh_set_graph drop the
+ * walks; so does lh_walk_detach, returning to arc draws.  The batched launch does not
+ * take handles with walks (LH_ERR_UNSUPPORTED), and lh_tune times arc draws. */
+LH_API lh_status lh_walk_build(lh_handle *h, int32_t walk_length, int32_t window, int64_t walks_per_batch,
+                               void *persist, size_t persist_bytes, void *scratch, size_t scratch_bytes);
+LH_API lh_status lh_walk_detach(lh_handle *h);
+
+/* The positive pairs (u, v) of samples [first, first + count) from the walks, exactly as
+ * training takes them (the same buffer fills).  u, v: device int32[count], caller-owned.
+ * Enqueued.  LH_ERR_NOT_BUILT before lh_walk_build; LH_ERR_INVALID_ARG for a NULL output
+ * or a range that wraps past 2^64 or has count >= 2^40. */
+LH_API lh_status lh_walk_pairs(lh_handle *h, uint64_t first, uint64_t count, int32_t *u, int32_t *v);
+
+/* Copy out the walk rows (device, caller-owned): offsets int64[n + 1] (row x is entries
+ * offsets[x] .. offsets[x + 1]), and per entry i the encoded discrete(N(x)): thr
+ * uint64[2m], keep int32[2m] (the entry's head, kept when a draw's threshold word is
+ * below thr[i]) and alias int32[2m] (the head of its alias entry otherwise).
+ * Synchronises the stream.  LH_ERR_NOT_BUILT before lh_walk_build. */
+LH_API lh_status lh_walk_export(lh_handle *h, int64_t *offsets, uint64_t *thr, int32_t *keep, int32_t *alias);
 
 /* Number of exported entry points (for load checks) and their names. */
 LH_API int lh_abi_symbol_count(void);

@@ -99,6 +99,48 @@ class Trainer:
     def init_embeddings(self):
         _lib.lh_init_embeddings(self.h)
 
+    def build_walks(self, walk_length: int = 100, window: int = 2, walks_per_batch: int = 1024):
+        """Switch the positive pairs to random walks (Sec. IV-B, Algorithms 2-3): builds the
+        walk graph's rows and per-row alias tables; later training and sampling calls take
+        their pairs from the walks."""
+        torch = self.torch
+        persist, scratch_bytes = _lib.lh_walk_size(self.n, self.m, walk_length, window, walks_per_batch)
+        with torch.cuda.stream(self.stream):
+            self.walk_mem = torch.empty(persist + 256, dtype=torch.uint8, device=self.device)
+            scratch = torch.empty(scratch_bytes + 256, dtype=torch.uint8, device=self.device)
+        _lib.lh_walk_build(self.h, walk_length, window, walks_per_batch, (self.walk_mem.data_ptr() + 255) // 256 * 256,
+                           persist, (scratch.data_ptr() + 255) // 256 * 256, scratch_bytes)
+        del scratch  # lh_walk_build synchronised the stream
+        self.walk_shape = (int(walk_length), int(window), int(walks_per_batch))
+
+    def walk_pairs(self, first: int, count: int):
+        """(u, v) of samples [first, first + count) from the walks, as training takes them."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            u = torch.empty(max(count, 1), dtype=torch.int32, device=self.device)
+            v = torch.empty(max(count, 1), dtype=torch.int32, device=self.device)
+        _lib.lh_walk_pairs(self.h, first, count, u.data_ptr(), v.data_ptr())
+        self.stream.synchronize()
+        return u[:count], v[:count]
+
+    def walk_export(self):
+        """(row offsets int64 [n + 1], thr uint64 [2m], keep int32 [2m], alias int32 [2m]) of
+        the walk rows as numpy arrays: entry i keeps its head keep[i] when the draw's
+        threshold word is below thr[i], else yields alias[i]."""
+        import numpy as np
+        torch = self.torch
+        E = 2 * self.m
+        with torch.cuda.stream(self.stream):
+            off = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+            thr = torch.empty(E, dtype=torch.int64, device=self.device)
+            keep = torch.empty(E, dtype=torch.int32, device=self.device)
+            al = torch.empty(E, dtype=torch.int32, device=self.device)
+        _lib.lh_walk_export(self.h, off.data_ptr(), thr.data_ptr(), keep.data_ptr(), al.data_ptr())
+        return off.cpu().numpy(), thr.cpu().numpy().view(np.uint64), keep.cpu().numpy(), al.cpu().numpy()
+
+    def detach_walks(self):
+        _lib.lh_walk_detach(self.h)
+
     def import_alias(self, which: int, thr, alias):
         torch = self.torch
         self._after_caller()

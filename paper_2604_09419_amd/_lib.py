@@ -95,6 +95,11 @@ def lib() -> ctypes.CDLL:
         "lh_batch_config": [P, ctypes.POINTER(ctypes.c_int64 * 3)],
         "lh_batch_done": [P, P],
         "lh_batch_destroy": [P],
+        "lh_walk_size": [i64, i64, ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "lh_walk_build": [P, ctypes.c_int32, ctypes.c_int32, i64, P, sz, P, sz],
+        "lh_walk_pairs": [P, u64, u64, P, P],
+        "lh_walk_export": [P, P, P, P, P],
+        "lh_walk_detach": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -259,6 +264,32 @@ def lh_batch_done(b, G: int):
 
 def lh_batch_destroy(b):
     check(lib().lh_batch_destroy(b), "lh_batch_destroy")
+
+
+def lh_walk_size(n: int, m: int, walk_length: int, window: int, walks_per_batch: int):
+    persist, scratch = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().lh_walk_size(n, m, walk_length, window, walks_per_batch, ctypes.byref(persist),
+                             ctypes.byref(scratch)), "lh_walk_size")
+    return persist.value, scratch.value
+
+
+def lh_walk_build(h, walk_length: int, window: int, walks_per_batch: int, persist_ptr: int, persist_bytes: int,
+                  scratch_ptr: int, scratch_bytes: int):
+    check(lib().lh_walk_build(h, walk_length, window, walks_per_batch, persist_ptr or None, persist_bytes,
+                              scratch_ptr or None, scratch_bytes), "lh_walk_build", h)
+
+
+def lh_walk_pairs(h, first: int, count: int, u_ptr: int, v_ptr: int):
+    check(lib().lh_walk_pairs(h, first, count, u_ptr or None, v_ptr or None), "lh_walk_pairs", h)
+
+
+def lh_walk_export(h, off_ptr: int, thr_ptr: int, keep_ptr: int, alias_ptr: int):
+    check(lib().lh_walk_export(h, off_ptr or None, thr_ptr or None, keep_ptr or None, alias_ptr or None),
+          "lh_walk_export", h)
+
+
+def lh_walk_detach(h):
+    check(lib().lh_walk_detach(h), "lh_walk_detach", h)
 
 
 def lh_abi_symbols():

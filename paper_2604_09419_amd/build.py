@@ -28,7 +28,7 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"),
 ]
 # The alias construction must round every binary64 operation on its own.
-PER_FILE = {"alias.hip": ["-ffp-contract=off"]}
+PER_FILE = {"alias.hip": ["-ffp-contract=off"], "walk.hip": ["-ffp-contract=off"]}
 
 
 def _headers_mtime() -> float:

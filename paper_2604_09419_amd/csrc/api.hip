@@ -52,6 +52,9 @@ GraphDev graph_dev(const lh_handle *h)
     for (int t = 0; t < 3; ++t) g.shadow[t] = shadowed ? sc.shadow[t] : nullptr;
     g.slot = shadowed ? sc.slot : nullptr;
     g.tiles = h->ws ? (unsigned long long *)(h->ws + h->lay.tiles) : nullptr;
+    g.pairs = nullptr;
+    g.pairs_first = 0;
+    g.heat = h->ws ? (const uint8_t *)(h->ws + h->lay.nheat) : nullptr;
     return g;
 }
 
@@ -119,6 +122,7 @@ static const char *const kSymbols[] = {
     "lh_read_embeddings", "lh_write_embeddings", "lh_check",       "lh_last_train_ms",   "lh_tune",   "lh_kernel_config", "lh_set_kernel_config",
     "lh_status_string",   "lh_last_error",     "lh_destroy",       "lh_batch_create",    "lh_batch_tune",
     "lh_batch_capture",   "lh_batch_launch",   "lh_batch_run",     "lh_batch_last_ms",   "lh_batch_config",    "lh_batch_done",      "lh_batch_destroy",
+    "lh_walk_size",       "lh_walk_build",     "lh_walk_pairs",    "lh_walk_export",     "lh_walk_detach",
     "lh_abi_symbol_count", "lh_abi_symbol_name",
 };
 
@@ -212,6 +216,7 @@ lh_status lh_bind(lh_handle *h, void *workspace, size_t bytes, void *const table
     h->stream = (hipStream_t)stream;
     h->bound = true;
     h->graph_set = h->edge_ready = h->neg_ready = false;
+    h->walk = WalkState();
     return LH_OK;
 }
 
@@ -234,6 +239,7 @@ lh_status lh_set_graph(lh_handle *h, int64_t n, int64_t m, const int32_t *src, c
     h->nrec = (NegRec *)(h->ws + L.nrec);
     h->graph_set = false;
     h->edge_ready = h->neg_ready = false;
+    h->walk = WalkState();
     DeviceGuard g(h->device);
     lh_status st = validate_graph(h);
     if (st != LH_OK) return st;
@@ -290,6 +296,16 @@ lh_status lh_sample(lh_handle *h, uint64_t first, uint64_t count, int32_t *u, in
     if (first + count < first) return fail(h, LH_ERR_INVALID_ARG, "sample range overflows");
     if (count >= (1ull << 40)) return fail(h, LH_ERR_INVALID_ARG, "count too large");
     DeviceGuard g(h->device);
+    if (h->walk.ready)
+        return walk_each_chunk(h, first, count,
+                               [&](unsigned long long sf, unsigned long long sc, const int2 *pairs,
+                                   unsigned long long pf) -> lh_status {
+                                   const unsigned long long o = sf - first;
+                                   launch_sample(h, sf, sc, u + o, v + o, neg ? neg + o * (unsigned long long)h->p.K : nullptr,
+                                                 pairs, pf);
+                                   hipError_t e = hipGetLastError();
+                                   return e == hipSuccess ? LH_OK : hip_fail(h, e, "sample");
+                               });
     launch_sample(h, first, count, u, v, neg);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LH_OK : hip_fail(h, e, "sample");
@@ -308,17 +324,23 @@ lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count)
     DeviceGuard g(h->device);
     hipError_t e = hipEventRecord(h->ev0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "event");
-    lh_status st = LH_OK;
-    if (h->p.mode == LH_HOGWILD) {
-        ShadowCtx sc;
-        const bool shadowed = shadow_ctx(h, &sc);
-        e = launch_hogwild(graph_dev(h), h->p.dtype, h->p.orders, h->cfg, first, first + count, h->num_cu,
-                           shadowed ? &sc : nullptr, h->stream);
-        if (e != hipSuccess) return hip_fail(h, e, "hogwild launch");
-    } else {
-        st = train_snapshot(h, first, count);
-        if (st != LH_OK) return st;
-    }
+    // One pass over [sf, sf + sc) with positive pairs from `pairs` (NULL: arc draws).
+    auto pass = [&](unsigned long long sf, unsigned long long sc, const int2 *pairs,
+                    unsigned long long pf) -> lh_status {
+        if (h->p.mode == LH_HOGWILD) {
+            ShadowCtx shc;
+            const bool shadowed = shadow_ctx(h, &shc);
+            GraphDev gd = graph_dev(h);
+            gd.pairs = pairs;
+            gd.pairs_first = pf;
+            hipError_t le = launch_hogwild(gd, h->p.dtype, h->p.orders, h->cfg, sf, sf + sc, h->num_cu,
+                                           shadowed ? &shc : nullptr, h->stream);
+            return le == hipSuccess ? LH_OK : hip_fail(h, le, "hogwild launch");
+        }
+        return train_snapshot(h, sf, sc, pairs, pf);
+    };
+    lh_status st = h->walk.ready ? walk_each_chunk(h, first, count, pass) : pass(first, count, nullptr, 0);
+    if (st != LH_OK) return st;
     e = hipEventRecord(h->ev1, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "event");
     h->timed = true;

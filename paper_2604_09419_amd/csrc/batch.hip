@@ -486,6 +486,7 @@ lh_status lh_batch_create(lh_batch **out, int G, lh_handle *const *graphs)
         if (!h) return LH_ERR_INVALID_ARG;
         if (!h->bound || !h->graph_set || !h->edge_ready || !h->neg_ready) return LH_ERR_NOT_BUILT;
         if (h->p.mode != LH_HOGWILD || h->p.orders != LH_ORDER2) return LH_ERR_UNSUPPORTED;
+        if (h->walk.ready) return LH_ERR_UNSUPPORTED;  // the batched kernel draws arcs only
         if (h->p.dtype != graphs[0]->p.dtype || h->device != graphs[0]->device) return LH_ERR_UNSUPPORTED;
         if ((h->p.K <= 5) != (graphs[0]->p.K <= 5)) return LH_ERR_UNSUPPORTED;
         const int nu = h->p.dtype == LH_FP32 ? h->p.d : h->p.d / 2;  // 4-byte units per row

@@ -40,6 +40,17 @@ struct __attribute__((aligned(16))) NegRec {
 };
 static_assert(sizeof(NegRec) == 16, "NegRec is 16 bytes");
 
+// One entry of a walk row (the neighbourhood N(x) of the walk graph): the alias table
+// of discrete(N(x)) with both outcomes resolved to vertices, so one 16-byte read decides
+// a step: the entry keeps its own head when the draw's threshold word is below thr, else
+// it yields the head of its alias entry.
+struct __attribute__((aligned(16))) WalkRec {
+    unsigned long long thr;
+    int32_t keep;   // head of this entry
+    int32_t alias;  // head of the alias entry
+};
+static_assert(sizeof(WalkRec) == 16, "WalkRec is 16 bytes");
+
 // Device status word bits (accumulated with atomicOr, read by lh_check).
 enum : unsigned int {
     ST_OUT_OF_RANGE = 1u,

@@ -1,6 +1,7 @@
 // Internal host-side state of a linehip handle and the workspace layouts.
 #pragma once
 
+#include <functional>
 #include <string>
 
 #include "common.hpp"
@@ -35,7 +36,32 @@ struct GraphDev {
     // Hogwild: the launch's tile counter (device word, reset to 0 before each launch);
     // wavefronts take 64-sample tiles from it until none are left.
     unsigned long long *tiles;
+    // Positive pairs from random walks: pairs[s - pairs_first] is the (u, v) of sample s
+    // (every sample of the launch lies in the buffer); NULL: slot 0 draws an arc.  heat:
+    // per-node heat, for the write path of a walk pair's rows.
+    const int2 *pairs;
+    unsigned long long pairs_first;
+    const uint8_t *heat;
 };
+
+// The random-walk pair source of a handle (lh_walk_build).
+struct WalkState {
+    bool ready = false;
+    int L = 0, W = 0;                 // walk length (vertices), window
+    long long Bw = 0, P = 0;          // walks per batch, pairs per walk
+    long long chunk_walks = 0;        // walks whose pairs one buffer fill holds (a multiple of Bw)
+    long long *off = nullptr;         // [n + 1] row offsets of the walk graph
+    WalkRec *rec = nullptr;           // [2m] row entries
+    int2 *pairs = nullptr;            // [chunk_walks * P]
+    long long loaded = -1;            // the chunk the buffer holds (-1: none)
+};
+
+// Persistent walk memory: offsets, records, pair buffer (256-byte aligned pieces).
+struct WalkLayout {
+    size_t off = 0, rec = 0, pairs = 0, total = 0;
+    long long chunk_walks = 0, P = 0;
+};
+WalkLayout walk_layout(long long n, long long m, int L, int W, long long Bw);
 
 // A kernel configuration: lanes per sample, 4-byte units of a row per lane (a unit is one
 // binary32 value or two bfloat16 values) and workgroups per compute unit.
@@ -134,6 +160,7 @@ struct lh_handle {
     bool timed = false;
     lh::TileCfg cfg;  // chosen Hogwild kernel configuration
     bool cfg_pinned = false;  // set by lh_set_kernel_config or lh_tune: auto_cfg leaves it
+    lh::WalkState walk;       // random-walk pair source, when one is built
     std::string err;
 };
 
@@ -149,7 +176,7 @@ lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32
 lh_status export_alias(lh_handle *h, int which, uint64_t *thr, int32_t *alias);
 void launch_init(lh_handle *h);
 void launch_sample(lh_handle *h, unsigned long long first, unsigned long long count, int32_t *u,
-                   int32_t *v, int32_t *neg);
+                   int32_t *v, int32_t *neg, const int2 *pairs = nullptr, unsigned long long pairs_first = 0);
 void launch_rw(lh_handle *h, int table, long long row0, long long rows, float *buf, bool write);
 TileCfg default_cfg(int dtype, int d);
 TileCfg natural_cfg(int dtype, int d);
@@ -180,5 +207,19 @@ bool shadow_ctx(const lh_handle *h, ShadowCtx *out);
 // into the tables (stochastic rounding keyed by `first`).
 hipError_t shadow_begin(const ShadowCtx &sc, int hot_heat, hipStream_t s);
 hipError_t shadow_end(const ShadowCtx &sc, int hot_heat, unsigned long long first, hipStream_t s);
-lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count);
+lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count,
+                         const int2 *pairs = nullptr, unsigned long long pairs_first = 0);
+// Walk pair source: for each buffer fill (chunk) that overlaps [first, first + count),
+// generate its pairs unless the buffer holds them already, then call
+// body(sub_first, sub_count, pairs, pairs_first) for the overlap.
+lh_status walk_each_chunk(lh_handle *h, unsigned long long first, unsigned long long count,
+                          const std::function<lh_status(unsigned long long, unsigned long long, const int2 *,
+                                                        unsigned long long)> &body);
+// Stable LSD radix sort of (keys, values) on the low `bits` bits of the keys, 4-bit digits,
+// each thread ranking its items in order (so equal keys keep their input order).  ka/va
+// hold the input, kb/vb are the other buffers of the ping-pong; *kout/*vout receive the
+// buffers that hold the result.  hist: 16 * ceil(E / RADIX_TILE) words; ilev: the scan
+// levels of that many words.  E < 2^32.
+void radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, long long E, int bits, uint32_t *hist,
+                    uint32_t *ilev, hipStream_t s, uint32_t **kout, uint32_t **vout);
 }  // namespace lh

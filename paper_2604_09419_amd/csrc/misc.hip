@@ -192,7 +192,7 @@ hipError_t launch_hogwild(const GraphDev &g, int dtype, int orders, const TileCf
 
 // ---------------------------------------------------------------------------
 // Sampling: one thread per sample, with the draw functions phase A of the training tile
-// uses (draw_slot, load_edge_rec, edge_pick, neg_pick).
+// uses (draw_slot, load_pair_rec, edge_pick, neg_pick).
 // ---------------------------------------------------------------------------
 __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long long count, int32_t *u, int32_t *v,
                          int32_t *neg)
@@ -202,7 +202,7 @@ __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long lon
     const unsigned long long s = first + i;
     const SlotDraw de = draw_slot(g, s, 0, g.m);
     uint4 r0, r1;
-    load_edge_rec(g.erec, de.col, r0, r1);
+    load_pair_rec(g, s, de.col, r0, r1);
     int uu = 0, vv = 0;
     (void)edge_pick(r0, r1, de.x1, uu, vv);
     u[i] = uu;
@@ -217,9 +217,11 @@ __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long lon
 }
 
 void launch_sample(lh_handle *h, unsigned long long first, unsigned long long count, int32_t *u, int32_t *v,
-                   int32_t *neg)
+                   int32_t *neg, const int2 *pairs, unsigned long long pairs_first)
 {
     GraphDev g = graph_dev(h);
+    g.pairs = pairs;
+    g.pairs_first = pairs_first;
     if (count == 0) return;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)LH_CDIV(count, 256)), dim3(256), 0, h->stream, g, first, count, u,
                        v, neg);

@@ -78,6 +78,27 @@ __global__ void __launch_bounds__(RADIX_THREADS) k_radix_scatter(const uint32_t 
     }
 }
 
+void radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, long long E, int bits, uint32_t *hist,
+                    uint32_t *ilev, hipStream_t s, uint32_t **kout, uint32_t **vout)
+{
+    const int passes = (bits + 3) / 4;
+    const long long nblk = LH_CDIV(E, RADIX_TILE);
+    for (int ps = 0; ps < passes && E > 0; ++ps) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(RADIX_THREADS), 0, s, ka, E, 4 * ps, hist, nblk);
+        chunk_scan<OpAdd<uint32_t>>(hist, hist, 16 * nblk, ilev, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(RADIX_THREADS), 0, s, ka, va, kb, vb, E, 4 * ps,
+                           hist, nblk);
+        uint32_t *t = ka;
+        ka = kb;
+        kb = t;
+        t = va;
+        va = vb;
+        vb = t;
+    }
+    *kout = ka;
+    *vout = va;
+}
+
 // ---- segments ---------------------------------------------------------------
 __global__ void k_heads(const uint32_t *keys, long long E, uint32_t *flag)
 {
@@ -152,11 +173,14 @@ static hipError_t launch_contrib(const GraphDev &g, int dtype, int orders, const
     return launch_snap_t<uint16_t, 3>(g, c, b0, b1, num_cu, so, s);
 }
 
-lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count)
+lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long long count, const int2 *pairs,
+                         unsigned long long pairs_first)
 {
     const lh_params &p = h->p;
     const WsLayout &L = h->lay;
     GraphDev g = graph_dev(h);
+    g.pairs = pairs;
+    g.pairs_first = pairs_first;
     hipStream_t s = h->stream;
     const unsigned long long B = (unsigned long long)p.batch;
     const int nord = p.orders == 3 ? 2 : 1;
@@ -171,7 +195,6 @@ lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long l
     // key bits: keys < 3n
     int bits = 1;
     while (bits < 32 && (1ull << bits) < 3ull * (unsigned long long)h->n) ++bits;
-    const int passes = (bits + 3) / 4;
     TileCfg c = natural_cfg(p.dtype, p.d);
     const int apply_lps = c.lps;
 
@@ -183,21 +206,8 @@ lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long l
         SnapOut so{k0, v0, contrib, b0, nord};
         hipError_t e = launch_contrib(g, p.dtype, p.orders, c, b0, b1, h->num_cu, so, s);
         if (e != hipSuccess) return hip_fail(h, e, "snapshot contributions");
-        const long long nblk = LH_CDIV(E, RADIX_TILE);
-        uint32_t *ka = k0, *kb = k1, *va = v0, *vb = v1;
-        for (int ps = 0; ps < passes; ++ps) {
-            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(RADIX_THREADS), 0, s, ka, E, 4 * ps, hist,
-                               nblk);
-            chunk_scan<OpAdd<uint32_t>>(hist, hist, 16 * nblk, ilev, s);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(RADIX_THREADS), 0, s, ka, va, kb, vb, E,
-                               4 * ps, hist, nblk);
-            uint32_t *t = ka;
-            ka = kb;
-            kb = t;
-            t = va;
-            va = vb;
-            vb = t;
-        }
+        uint32_t *ka = k0, *va = v0;
+        radix_sort_u32(k0, v0, k1, v1, E, bits, hist, ilev, s, &ka, &va);
         const unsigned eb = (unsigned)LH_CDIV(E, 256);
         hipLaunchKernelGGL(k_heads, dim3(eb), dim3(256), 0, s, ka, E, segid);
         chunk_scan<OpAdd<uint32_t>>(segid, segid, E, ilev, s);

@@ -90,6 +90,23 @@ __device__ __forceinline__ void load_edge_rec(const EdgeRec *erec, long long col
     r1 = er[1];
 }
 
+// Slot 0's record words: the edge table's record of the drawn column (Algorithm 3's root
+// edge), or, when the positive pairs come from random walks, a record that yields the
+// sample's walk pair (u, v) whatever the threshold word (both outcomes are (u, v)), with
+// the heats of u and v in the record's heat word.
+__device__ __forceinline__ void load_pair_rec(const GraphDev &g, unsigned long long s, long long col, uint4 &r0,
+                                              uint4 &r1)
+{
+    if (g.pairs == nullptr) {
+        load_edge_rec(g.erec, col, r0, r1);
+        return;
+    }
+    const int2 p = g.pairs[s - g.pairs_first];
+    const unsigned hu = g.heat[p.x], hv = g.heat[p.y];
+    r0 = make_uint4(~0u, ~0u, 0u, (unsigned)p.x);
+    r1 = make_uint4((unsigned)p.y, (unsigned)p.x, (unsigned)p.y, hu | (hv << 8) | (hu << 16) | (hv << 24));
+}
+
 // The arc (u, v) a slot-0 draw picks from its record words (threshold r0.xy, column arc's
 // endpoints r0.w, r1.x, alias arc's r1.y, r1.z); returns whether the column kept itself.
 __device__ __forceinline__ bool edge_pick(const uint4 &r0, const uint4 &r1, unsigned long long x1, int &u, int &v)
@@ -540,7 +557,7 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
             // (which would hold 1 + K blocks of state in registers).
             const SlotDraw de = draw_slot(g, s, 0, g.m);
             uint4 r0, r1;
-            load_edge_rec(g.erec, de.col, r0, r1);
+            load_pair_rec(g, s, de.col, r0, r1);
             my_sr = (uint32_t)de.x2;
             __builtin_amdgcn_sched_barrier(0);
             SlotDraw dn[KMAX];

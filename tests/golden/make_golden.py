@@ -5,6 +5,8 @@
     python tests/golden/make_golden.py batch6_auc  # about a minute
     python tests/golden/make_golden.py batch6_bf16_auc  # about five minutes (bfloat16 storage, 8 streams)
     python tests/golden/make_golden.py mid_auc     # about a minute
+    python tests/golden/make_golden.py c2_walk_auc   # C2 with random-walk pairs: about 40 minutes
+    python tests/golden/make_golden.py mid_walk_auc  # the mid-size graph with random-walk pairs
 
 Each output JSON records the command, the workload and the oracle's binary64 result.
 """
@@ -22,16 +24,22 @@ import oracle  # noqa: E402
 from synth import CONFIGS, config_graph, mid_graph, small_batch  # noqa: E402
 
 
-def run_auc(name: str, orders: int, T: int, d: int, out: str):
+# Random-walk pair source of the walk workloads: walk length, window, walks per batch.
+WALK = dict(L=100, W=2, Bw=1024)
+
+
+def run_auc(name: str, orders: int, T: int, d: int, out: str, walks: bool = False):
     cfg = CONFIGS[name]
     t0 = time.time()
     g, hs, hd, neg = config_graph(name, holdout=True)
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
     m = oracle.Model(tb, d=d, K=cfg["K"], orders=orders, T=T, seed=cfg["seed"],
                      eta0=cfg["eta0"])
+    wg = oracle.WalkGraph(tb, **WALK) if walks else None
     res = {"workload": name, "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": d,
            "K": cfg["K"], "orders": orders, "T": T, "seed": cfg["seed"], "eta0": cfg["eta0"],
            "mode": "seq", "precision": "binary64",
+           "pairs": f"random walks {WALK}" if walks else "arc draws",
            "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
     def aucs(prefix):
         """Held-out AUC under each score: order 2 vertex.context (uc) and
@@ -48,7 +56,7 @@ def run_auc(name: str, orders: int, T: int, d: int, out: str):
             res[f"{prefix}auc_{k}"] = oracle.auc(p, q)
 
     aucs("init_")
-    m.train(0, T, "seq")
+    m.train(0, T, "seq", walks=wg)
     aucs("")
     res["oracle_seconds"] = round(time.time() - t0, 1)
     with open(os.path.join(HERE, out), "w") as f:
@@ -92,16 +100,17 @@ def run_batch6(out: str, storage: str = "binary64"):
         json.dump(res, f, indent=1)
 
 
-def run_mid(out: str):
+def run_mid(out: str, walks: bool = False):
     """Second-order held-out AUCs (uc, uu) of the mid-size workload, SEQ mode."""
     t0 = time.time()
     it = mid_graph()
     g, hs, hd, neg = it["graph"], it["held_src"], it["held_dst"], it["neg_dst"]
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
     m = oracle.Model(tb, d=it["d"], K=5, orders=2, T=it["T"], seed=it["seed"], graph_id=it["graph_id"])
-    m.train(0, it["T"], "seq")
+    m.train(0, it["T"], "seq", walks=oracle.WalkGraph(tb, **WALK) if walks else None)
     res = {"workload": "synth.mid_graph", "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": it["d"],
            "K": 5, "orders": 2, "T": it["T"], "seed": it["seed"], "mode": "seq", "precision": "binary64",
+           "pairs": f"random walks {WALK}" if walks else "arc draws",
            "auc_uc": oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2)),
            "auc_uu": oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg)),
            "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
@@ -123,5 +132,10 @@ if __name__ == "__main__":
         run_batch6("batch6_oracle_bf16_auc.json", storage="bf16")
     elif which == "mid_auc":
         run_mid("mid_oracle_auc.json")
+    elif which == "c2_walk_auc":
+        run_auc("C2", orders=3, T=CONFIGS["C2"]["T"], d=CONFIGS["C2"]["d"], out="c2_walk_oracle_auc.json",
+                walks=True)
+    elif which == "mid_walk_auc":
+        run_mid("mid_walk_oracle_auc.json", walks=True)
     else:
         raise SystemExit(__doc__)

@@ -104,6 +104,27 @@ def test_null_handles_rejected(L):
     cfg = (ctypes.c_int32 * 3)(64, 2, 2)
     assert L.lh_set_kernel_config(None, ctypes.byref(cfg)) == 1
     assert L.lh_kernel_config(None, ctypes.byref(cfg)) == 1
+    assert L.lh_walk_build(None, 100, 2, 1024, None, 0, None, 0) == 1
+    assert L.lh_walk_pairs(None, 0, 1, None, None) == 1
+    assert L.lh_walk_export(None, None, None, None, None) == 1
+    assert L.lh_walk_detach(None) == 1
+
+
+@pytest.mark.parametrize("n,m,L_,W,Bw,ok", [
+    (1000, 5000, 100, 2, 1024, True), (1000, 5000, 2, 2, 1, True), (1000, 5000, 100, 8, 16, True),
+    (1000, 5000, 1, 2, 1024, False), (1000, 5000, 100, 1, 1024, False), (1000, 5000, 100, 9, 1024, False),
+    (1000, 5000, 4, 5, 1024, False), (1000, 5000, 100, 2, 0, False), (1000, 0, 100, 2, 1024, False),
+    (0, 5000, 100, 2, 1024, False), (1000, 1 << 31, 100, 2, 1024, False), (1000, 5000, 4097, 2, 1, False),
+    (1000, 5000, 100, 2, (1 << 27) // 99 + 1, False)])
+def test_walk_sizes_and_ranges(L, n, m, L_, W, Bw, ok):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    st = L.lh_walk_size(n, m, L_, W, Bw, ctypes.byref(a), ctypes.byref(b))
+    assert (st == 0) == ok, st
+    if ok:
+        P = sum(L_ - dl for dl in range(1, W))
+        # rows: offsets and 16-byte entries; the pair buffer holds whole walk batches
+        assert a.value >= 8 * (n + 1) + 16 * 2 * m + 8 * Bw * P
+        assert b.value >= 32 * 2 * m
 
 
 def test_create_without_device_reports_no_device():

@@ -1,0 +1,264 @@
+"""Parity of the random-walk pair source (Sec. IV-B, Algorithms 2-3) on the GPU with the
+oracle, through the C ABI.
+
+Integer work (the walk rows and their per-row alias tables, the walk pairs, whole
+sampled tuples) must match bit for bit; SNAPSHOT training on walk pairs must agree with
+the binary64 oracle within 1e-5 relative error per row; Hogwild training on walk pairs
+must match the oracle's held-out AUC within 0.005.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_graph
+from synth.graphs import Graph
+
+from gpu_util import dot_rows, max_row_rel_err, trainer_for
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+WALK = dict(L=100, W=2, Bw=1024)  # the walk workloads' walk length, window, walks per batch
+
+
+def _lh():
+    import paper_2604_09419_amd as lh
+    return lh
+
+
+def _rand_graph(n, m, seed, zero_frac=0.0):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, size=m).astype(np.int32)
+    dst = rng.integers(0, n, size=m).astype(np.int32)
+    w = rng.lognormal(0, 1.5, size=m).astype(np.float32)
+    if zero_frac:
+        w[rng.random(m) < zero_frac] = 0.0
+        w[0] = 1.0
+    return Graph(n=n, src=src, dst=dst, w=w)
+
+
+def _star_graph(leaves):
+    """Vertex 0 joined to `leaves` others in both directions at random weights, plus a
+    ring over the leaves: row 0 spans more than 1024 scan chunks (two levels of chunk
+    totals)."""
+    rng = np.random.default_rng(leaves)
+    n = leaves + 1
+    lv = np.arange(1, n, dtype=np.int32)
+    src = np.concatenate([np.zeros(leaves, np.int32), lv, lv])
+    dst = np.concatenate([lv, np.zeros(leaves, np.int32), np.roll(lv, 1)])
+    w = rng.lognormal(0, 1.0, size=src.size).astype(np.float32)
+    return Graph(n=n, src=src, dst=dst, w=w)
+
+
+def _oracle_walk(g, L, W, Bw):
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    return t, oracle.WalkGraph(t, L=L, W=W, Bw=Bw)
+
+
+def _rows_equal(tr, wg):
+    off, thr, keep, al = tr.walk_export()
+    assert np.array_equal(off, wg.off)
+    assert np.array_equal(thr, wg.thr)
+    assert np.array_equal(keep, wg.nbr)
+    rows = np.repeat(np.arange(wg.off.size - 1), np.diff(wg.off))
+    assert np.array_equal(al, wg.nbr[wg.off[rows] + wg.alias])
+
+
+# ---------------------------------------------------------------------------
+# Walk rows: bitwise equal to the oracle's.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["c1", "random_zero_weights", "isolated", "one_arc", "star_3000", "star_2M"])
+def test_walk_rows_bitwise(case):
+    if case == "c1":
+        g, _, _, _ = config_graph("C1")
+    elif case == "random_zero_weights":
+        g = _rand_graph(5000, 60_000, 3, zero_frac=0.2)
+    elif case == "isolated":
+        g = _rand_graph(200_000, 3000, 4)  # most vertices have no arc
+    elif case == "one_arc":
+        g = Graph(n=3, src=np.array([2], np.int32), dst=np.array([0], np.int32), w=np.array([0.5], np.float32))
+    elif case == "star_3000":
+        g = _star_graph(3000)
+    else:
+        g = _star_graph(1 << 21)
+    print(f"walk rows {case}: n={g.n} m={g.m}", flush=True)
+    tr = trainer_for(g, d=8, K=2, orders=2, seed=5, total_samples=10, init=False)
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    _, wg = _oracle_walk(g, **WALK)
+    _rows_equal(tr, wg)
+    tr.close()
+
+
+# ---------------------------------------------------------------------------
+# Walk pairs and sampled tuples: bitwise.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,W,Bw", [(100, 2, 1024), (7, 3, 5), (2, 2, 1), (40, 8, 33)])
+def test_walk_pairs_bitwise(L, W, Bw):
+    g, _, _, _ = config_graph("C1")
+    tr = trainer_for(g, d=8, K=3, orders=2, seed=9, total_samples=10, graph_id=3, init=False)
+    tr.build_walks(walk_length=L, window=W, walks_per_batch=Bw)
+    t, wg = _oracle_walk(g, L, W, Bw)
+    per = Bw * wg.pairs_per_walk
+    for first, count in [(0, 100_003), (max(0, per - 17), 2 * per + 40), (2**33 + 7, 50_000), (2**41 + 5, 4097)]:
+        print(f"walk pairs L={L} W={W} Bw={Bw}: [{first}, {first + count})", flush=True)
+        u, v = tr.walk_pairs(first, count)
+        ou, ov = wg.pairs(seed=9, graph_id=3, first=first, count=count)
+        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov), first
+    # tuples: the walk pair and the usual negatives
+    for first in (0, 2**32 + 3):
+        u, v, neg = tr.sample(first, 20_000)
+        ou, ov = wg.pairs(seed=9, graph_id=3, first=first, count=20_000)
+        oneg = oracle.sample_negatives(g.n, t.nthr, t.nalias, seed=9, graph_id=3, K=3, first=first, count=20_000)
+        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov)
+        assert np.array_equal(neg.cpu().numpy(), oneg)
+    tr.close()
+
+
+def test_walk_pairs_across_buffer_fills():
+    """Ranges that span two fills of the pair buffer (about 2^24 pairs each), read twice
+    in an order that forces refills, equal the oracle's."""
+    g, _, _, _ = config_graph("C1")
+    tr = trainer_for(g, d=8, K=1, orders=2, seed=2, total_samples=10, init=False)
+    tr.build_walks(walk_length=100, window=2, walks_per_batch=1024)
+    _, wg = _oracle_walk(g, 100, 2, 1024)
+    per = 1024 * 99
+    fill = per * ((1 << 24) // per)
+    ranges = [(fill - 3000, 6000), (5, 1000), (fill - 3000, 6000), (3 * fill + 11, 2000)]
+    for first, count in ranges:
+        u, v = tr.walk_pairs(first, count)
+        ou, ov = wg.pairs(seed=2, graph_id=0, first=first, count=count)
+        assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov), first
+    tr.close()
+
+
+def test_detach_returns_to_arc_draws():
+    g, _, _, _ = config_graph("C1")
+    t = oracle.Tables(g.n, g.src, g.dst, g.w)
+    tr = trainer_for(g, d=8, K=2, orders=2, seed=4, total_samples=10, init=False)
+    tr.build_walks(walk_length=10, window=2, walks_per_batch=8)
+    tr.detach_walks()
+    u, v, neg = tr.sample(100, 5000)
+    ou, ov, oneg = oracle.sample(t, seed=4, graph_id=0, K=2, first=100, count=5000)
+    assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov)
+    assert np.array_equal(neg.cpu().numpy(), oneg)
+    tr.close()
+
+
+# ---------------------------------------------------------------------------
+# Training on walk pairs.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B,orders,K", [(1024, 2, 5), (99, 3, 1), (3168, 1, 0)])
+def test_walk_snapshot_c1_within_1e5(B, orders, K):
+    """SNAPSHOT on walk pairs (batches inside walk batches: B divides 1024 x 99) against
+    the binary64 oracle's SNAPSHOT on the same pairs."""
+    lh = _lh()
+    g, _, _, _ = config_graph("C1")
+    t, wg = _oracle_walk(g, **WALK)
+    count = 1024 * 99 * 3 + 7 * B if B > 1 else 1000
+    T = 1_000_000
+    tr = trainer_for(g, d=16, K=K, orders=orders, seed=1, total_samples=T, mode="snapshot", batch=B, lam=0.01,
+                     alpha_neg=0.8)
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    m = oracle.Model(t, d=16, K=K, orders=orders, T=T, seed=1, lam=0.01, alpha=0.8)
+    tr.train_steps(0, count)
+    m.train(0, count, "snapshot", B, walks=wg)
+    tr.check()
+    for name, tab, ref in (("U", lh.LH_TABLE_U, m.U), ("C", lh.LH_TABLE_C, m.C), ("U1", lh.LH_TABLE_U1, m.U1)):
+        if ref is None:
+            continue
+        err = max_row_rel_err(tr.read(tab).cpu().numpy(), ref)
+        print(f"walk snapshot B={B} orders={orders} K={K} {name}: max row rel err {err:.3e}", flush=True)
+        assert err <= 1e-5, (name, err)
+
+
+def test_walk_snapshot_batch_must_divide_a_walk_batch():
+    lh = _lh()
+    g, _, _, _ = config_graph("C1")
+    tr = trainer_for(g, d=8, K=1, orders=2, seed=1, total_samples=1000, mode="snapshot", batch=1000)
+    with pytest.raises(lh._lib.LhError):
+        tr.build_walks(walk_length=100, window=2, walks_per_batch=1024)
+    tr.close()
+
+
+def _aucs(tr, hs, hd, neg):
+    lh = _lh()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    return (oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg)),
+            oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg)))
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_walk_hogwild_c1_auc_matches_oracle(dtype):
+    from synth import CONFIGS
+    cfg = CONFIGS["C1"]
+    g, hs, hd, neg = config_graph("C1", holdout=True)
+    t, wg = _oracle_walk(g, **WALK)
+    m = oracle.Model(t, d=16, K=5, orders=2, T=cfg["T"], seed=cfg["seed"], eta0=cfg["eta0"])
+    m.train(0, cfg["T"], "seq", walks=wg)
+    ref = (oracle.auc(m.scores(hs, hd, 2), m.scores(hs, neg, 2)),
+           oracle.auc(oracle.pair_scores(m.U, m.U, hs, hd), oracle.pair_scores(m.U, m.U, hs, neg)))
+    tr = trainer_for(g, d=16, K=5, orders=2, dtype=dtype, seed=cfg["seed"], total_samples=cfg["T"])
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    tr.train_steps(0, cfg["T"])
+    tr.check()
+    got = _aucs(tr, hs, hd, neg)
+    print(f"C1 walks {dtype}: uc {got[0]:.4f} (oracle {ref[0]:.4f}) uu {got[1]:.4f} (oracle {ref[1]:.4f})", flush=True)
+    assert abs(got[0] - ref[0]) <= 0.005 and abs(got[1] - ref[1]) <= 0.005
+    tr.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_walk_hogwild_mid_graph_auc_matches_oracle(dtype):
+    from synth import mid_graph
+    gold = json.load(open(os.path.join(GOLDEN, "mid_walk_oracle_auc.json")))
+    it = mid_graph()
+    g, hs, hd, neg = it["graph"], it["held_src"], it["held_dst"], it["neg_dst"]
+    assert (g.n, g.m, hs.size, it["T"]) == (gold["n"], gold["m_train"], gold["held_out"], gold["T"])
+    tr = trainer_for(g, d=it["d"], K=5, orders=2, dtype=dtype, seed=it["seed"], total_samples=it["T"])
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    tr.train_steps(0, it["T"])
+    tr.check()
+    uc, uu = _aucs(tr, hs, hd, neg)
+    print(f"mid graph walks {dtype}: uc {uc:.4f} (oracle {gold['auc_uc']:.4f}) uu {uu:.4f} "
+          f"(oracle {gold['auc_uu']:.4f})", flush=True)
+    assert abs(uc - gold["auc_uc"]) <= 0.005 and abs(uu - gold["auc_uu"]) <= 0.005
+    tr.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_walk_hogwild_c2_auc_matches_oracle(dtype):
+    from synth import CONFIGS
+    lh = _lh()
+    gold = json.load(open(os.path.join(GOLDEN, "c2_walk_oracle_auc.json")))
+    cfg = CONFIGS["C2"]
+    g, hs, hd, neg = config_graph("C2", holdout=True)
+    assert (g.n, g.m, hs.size) == (gold["n"], gold["m_train"], gold["held_out"])
+    tr = trainer_for(g, d=cfg["d"], K=cfg["K"], orders=3, dtype=dtype, seed=cfg["seed"], total_samples=cfg["T"])
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    tr.train_steps(0, cfg["T"])
+    tr.check()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    U1 = tr.read(lh.LH_TABLE_U1).cpu().numpy()
+    uu = (dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
+    o1 = (dot_rows(U1, U1, hs, hd), dot_rows(U1, U1, hs, neg))
+    got = {"uc": oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg)), "uu": oracle.auc(*uu),
+           "o1": oracle.auc(*o1), "concat": oracle.auc(uu[0] + o1[0], uu[1] + o1[1])}
+    for k, v in got.items():
+        print(f"C2 walks {dtype} {k}: {v:.4f} (oracle {gold['auc_' + k]:.4f})", flush=True)
+    for k, v in got.items():
+        assert abs(v - gold["auc_" + k]) <= 0.005, k
+    tr.close()
+
+
+def test_batched_launch_refuses_walk_handles():
+    lh = _lh()
+    g, _, _, _ = config_graph("C1")
+    tr = trainer_for(g, d=16, K=5, orders=2, seed=1, total_samples=1000)
+    tr.build_walks(walk_length=10, window=2, walks_per_batch=4)
+    with pytest.raises(lh._lib.LhError):
+        lh.BatchTrainer([tr])
+    tr.close()
