@@ -191,6 +191,43 @@ def walk_legs(args, cfg, g, hs, hd, neg, seed, T):
     return out
 
 
+def node_classification(args):
+    """Sec. V-A's quality metric on the labelled stand-in graph (synth.labels.SBM): Micro-
+    and Macro-F1 of a one-vs-rest logistic regression on 10 % of the labels, for vertex
+    embeddings trained on the GPU with arc-draw and with random-walk pairs, beside the
+    oracle's stored values."""
+    import torch
+    from paper_2604_09419_amd import LH_TABLE_U, Trainer
+    from synth.labels import node_classification_f1, sbm_workload
+    g, labels, c = sbm_workload()
+    out = {"workload": f"stochastic block model: {g.n} nodes, {c['classes']} classes, mean degree "
+                       f"{c['mean_degree']}, p_in {c['p_in']}; d={c['d']}, K={c['K']}, second order, "
+                       f"{c['epochs']} epochs (T={c['T']})"}
+    for dtype in ("fp32", "bf16"):
+        for pairs in ("arcs", "walks"):
+            tr = Trainer(g.n, g.src, g.dst, g.w, d=c["d"], K=c["K"], orders=c["orders"], dtype=dtype,
+                         eta0=c["eta0"], seed=c["train_seed"], total_samples=c["T"])
+            if pairs == "walks":
+                tr.build_walks(**WALK)
+            tr.train_steps(0, c["T"])
+            ms = tr.last_train_ms()
+            micro, macro = node_classification_f1(tr.read(LH_TABLE_U).cpu().numpy(), labels, c["split_seed"])
+            out[f"{dtype}_{pairs}"] = {"micro_f1": micro, "macro_f1": macro, "train_ms": ms}
+            tr.close()
+            del tr
+            torch.cuda.empty_cache()
+    gold_path = os.path.join(GOLDEN, "sbm_oracle_f1.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        out["oracle_binary64"] = {p: {"micro_f1": gold[p]["micro"], "macro_f1": gold[p]["macro"]} for p in ("arcs", "walks")}
+        # the tolerance of the tests: max(0.01, 3 sd of the oracle's F1 over training seeds)
+        def ok(v, ref):
+            return all(abs(v[f"{a}_f1"] - ref[a]) <= max(0.01, 3.0 * ref[f"sd_{a}"]) for a in ("micro", "macro"))
+        out["within_tolerance_of_oracle"] = all(ok(v, gold[k.split("_")[1]]) for k, v in out.items()
+                                                if isinstance(v, dict) and "micro_f1" in v)
+    return out
+
+
 def held_out_auc(tr, hs, hd, neg, orders):
     import numpy as np
     from paper_2604_09419_amd import LH_TABLE_C, LH_TABLE_U, LH_TABLE_U1
@@ -503,6 +540,7 @@ def main():
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
     ap.add_argument("--no-walks", action="store_true", help="skip the random-walk pair legs")
+    ap.add_argument("--no-f1", action="store_true", help="skip the node-classification leg")
     ap.add_argument("--hot-shadow", action="store_true",
                     help="bfloat16 runs: hot rows accumulate in a binary32 shadow per launch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
@@ -612,6 +650,9 @@ def main():
 
     if not args.no_walks:
         result["walks"] = walk_legs(args, cfg, g, hs, hd, neg, seed, T)
+    if not args.no_f1:
+        result["node_classification"] = node_classification(args)
+        log(f"[bench] node classification {result['node_classification']}")
 
     gold_path = os.path.join(GOLDEN, "c2_oracle_auc.json")
     if os.path.exists(gold_path):

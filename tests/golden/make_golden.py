@@ -7,6 +7,7 @@
     python tests/golden/make_golden.py mid_auc     # about a minute
     python tests/golden/make_golden.py c2_walk_auc   # C2 with random-walk pairs: about 40 minutes
     python tests/golden/make_golden.py mid_walk_auc  # the mid-size graph with random-walk pairs
+    python tests/golden/make_golden.py sbm_f1        # labelled graph, node-classification F1: about 10 minutes
 
 Each output JSON records the command, the workload and the oracle's binary64 result.
 """
@@ -120,6 +121,44 @@ def run_mid(out: str, walks: bool = False):
     print(json.dumps(res))
 
 
+def _sbm_run(args):
+    pairs, train_seed = args
+    from synth.labels import node_classification_f1, sbm_workload
+    g, labels, c = sbm_workload()
+    tb = oracle.Tables(g.n, g.src, g.dst, g.w)
+    m = oracle.Model(tb, d=c["d"], K=c["K"], orders=c["orders"], T=c["T"], seed=train_seed, eta0=c["eta0"])
+    m.train(0, c["T"], "seq", walks=oracle.WalkGraph(tb, **WALK) if pairs == "walks" else None)
+    return pairs, train_seed, node_classification_f1(m.U, labels, c["split_seed"])
+
+
+def run_sbm_f1(out: str):
+    """Node-classification Micro/Macro-F1 (Sec. V-A) of the labelled workload's vertex
+    embeddings U, trained by the oracle (SEQ, binary64) with arc-draw pairs and with
+    random-walk pairs; the workload's training seed, plus two more seeds whose spread
+    sizes the tolerance of the GPU comparison."""
+    from concurrent.futures import ProcessPoolExecutor
+    from synth.labels import SBM, sbm_workload
+    t0 = time.time()
+    g, _, c = sbm_workload()
+    seeds = [c["train_seed"], 70, 71]
+    jobs = [(p, s) for p in ("arcs", "walks") for s in seeds]
+    with ProcessPoolExecutor(max_workers=len(jobs)) as ex:
+        results = list(ex.map(_sbm_run, jobs))
+    res = {"workload": "synth.labels.SBM", "config": SBM, "n": g.n, "m": g.m, "T": c["T"], "mode": "seq",
+           "precision": "binary64", "walk": WALK, "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    for pairs in ("arcs", "walks"):
+        rows = {s: f for p, s, f in results if p == pairs}
+        mi = [rows[s][0] for s in seeds]
+        ma = [rows[s][1] for s in seeds]
+        res[pairs] = {"micro": rows[c["train_seed"]][0], "macro": rows[c["train_seed"]][1],
+                      "micro_by_seed": dict(zip(map(str, seeds), mi)), "macro_by_seed": dict(zip(map(str, seeds), ma)),
+                      "sd_micro": float(np.std(mi, ddof=1)), "sd_macro": float(np.std(ma, ddof=1))}
+    res["oracle_seconds"] = round(time.time() - t0, 1)
+    with open(os.path.join(HERE, out), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 if __name__ == "__main__":
     which = sys.argv[1]
     if which == "c1_auc":
@@ -137,5 +176,7 @@ if __name__ == "__main__":
                 walks=True)
     elif which == "mid_walk_auc":
         run_mid("mid_walk_oracle_auc.json", walks=True)
+    elif which == "sbm_f1":
+        run_sbm_f1("sbm_oracle_f1.json")
     else:
         raise SystemExit(__doc__)

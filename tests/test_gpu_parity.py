@@ -439,11 +439,10 @@ def test_c5_negative_table_and_negatives_bitwise():
         assert np.array_equal(neg, ref), first
 
 
-@pytest.mark.skipif(os.environ.get("LH_C5_EDGE") != "1",
-                    reason="about 75 GB of host memory and several minutes of oracle time: set LH_C5_EDGE=1")
 def test_c5_edge_table_and_tuples_bitwise():
     """C5's 2^30-arc edge alias table equals the oracle's bit for bit, and whole tuples
-    (u, v, negatives) of samples at 0, 2^32 and 2^41 + 3 are the oracle's."""
+    (u, v, negatives) of samples at 0, 2^32 and 2^41 + 3 are the oracle's.  (About 75 GB
+    of host memory and a minute of oracle time.)"""
     import time
     lh = _lh()
     c, src, dst, w = _c5_graph_on_gpu()
