@@ -219,11 +219,16 @@ def node_classification(args):
     gold_path = os.path.join(GOLDEN, "sbm_oracle_f1.json")
     if os.path.exists(gold_path):
         gold = json.load(open(gold_path))
-        out["oracle_binary64"] = {p: {"micro_f1": gold[p]["micro"], "macro_f1": gold[p]["macro"]} for p in ("arcs", "walks")}
+        out["oracle"] = {k: {"micro_f1": gold[k]["micro"], "macro_f1": gold[k]["macro"]}
+                         for k in ("arcs", "walks", "arcs_bf16", "walks_bf16") if k in gold}
         # the tolerance of the tests: max(0.01, 3 sd of the oracle's F1 over training seeds)
         def ok(v, ref):
             return all(abs(v[f"{a}_f1"] - ref[a]) <= max(0.01, 3.0 * ref[f"sd_{a}"]) for a in ("micro", "macro"))
-        out["within_tolerance_of_oracle"] = all(ok(v, gold[k.split("_")[1]]) for k, v in out.items()
+        # bfloat16 runs against the oracle with bfloat16 storage
+        def ref_of(k):
+            dtype, pairs = k.split("_")
+            return gold[pairs if dtype == "fp32" else pairs + "_bf16"]
+        out["within_tolerance_of_oracle"] = all(ok(v, ref_of(k)) for k, v in out.items()
                                                 if isinstance(v, dict) and "micro_f1" in v)
     return out
 

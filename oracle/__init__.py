@@ -28,7 +28,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so`` (no contraction, no fast-math)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp"
+        tmp = f"{_SO}.{os.getpid()}.tmp"  # processes that build at once each write their own file
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -92,6 +92,9 @@ def lib():
             L.or_train_walk.argtypes = [P, P, i64, i64, P, P, P, P, P, P, P, P, i32, i32, i64, u64, u32,
                                         i32, i32, i32, f64, f64, f64, u64, P, P, P, u64, u64, i32, u64]
             L.or_train_walk.restype = i32
+            L.or_train_bf16_walk.argtypes = [P, P, i64, i64, P, P, P, P, P, P, P, P, i32, i32, i64, u64,
+                                             u32, i32, i32, i32, f64, f64, f64, u64, P, P, P, u64, u64, u64]
+            L.or_train_bf16_walk.restype = i32
         _lib = L
     return _lib
 
@@ -321,9 +324,20 @@ class Model:
         """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch).  ``walks``:
         positive pairs from that random-walk source instead of arc draws."""
         t = self.t
+        if walks is not None and self.storage == "bf16":
+            if mode != "seq":
+                raise ValueError("bfloat16 storage is modelled in SEQ mode only")
+            wg = walks
+            rc = lib().or_train_bf16_walk(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                                          _p(t.nthr), _p(t.nalias), _p(wg.off), _p(wg.nbr), _p(wg.thr),
+                                          _p(wg.alias), wg.L, wg.W, wg.Bw, self.seed, self.graph_id,
+                                          self.d, self.K, self.orders, self.eta0, self.lam, self.alpha,
+                                          self.T, _p(self.U), _p(self.C), _p(self.U1), first, count,
+                                          self.sr_stream)
+            if rc != 0:
+                raise ValueError("or_train_bf16_walk rejected its arguments")
+            return
         if walks is not None:
-            if self.storage != "binary64":
-                raise ValueError("walk pairs are modelled with binary64 storage")
             wg = walks
             rc = lib().or_train_walk(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
                                      _p(t.nthr), _p(t.nalias), _p(wg.off), _p(wg.nbr), _p(wg.thr),

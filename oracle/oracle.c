@@ -609,6 +609,24 @@ static int walker_ok(const or_walker *wk)
     return wk->L >= 2 && wk->W >= 2 && wk->W <= wk->L && wk->Bw >= 1 && wk->m >= 1;
 }
 
+/* The pairs of walk batch b in sample order: pu/pv[p Bw + j] = pair p of walk b Bw + j. */
+static void fill_walk_batch(const or_walker *wk, uint64_t b, int32_t *pu, int32_t *pv)
+{
+    const int L = wk->L, W = wk->W;
+    const uint64_t Bw = (uint64_t)wk->Bw, P = (uint64_t)walk_pairs_per_walk(L, W);
+    int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+    for (uint64_t j = 0; j < Bw; j++) {
+        walk_vertices(wk, b * Bw + j, vert);
+        for (uint64_t p = 0; p < P; p++) {
+            int a, c;
+            walk_pair_positions(L, W, (int64_t)p, &a, &c);
+            pu[p * Bw + j] = vert[a];
+            pv[p * Bw + j] = vert[c];
+        }
+    }
+    free(vert);
+}
+
 /* The positive pairs of samples [first, first + count). */
 int or_walk_pairs(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                   const uint64_t *ethr, const int32_t *ealias,
@@ -665,31 +683,22 @@ int or_train_walk(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
     if (mode == 1 && batch == 0) return 1;
     or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
     if (!walker_ok(&wk)) return 1;
-    const uint64_t P = (uint64_t)walk_pairs_per_walk(L, W), per = (uint64_t)Bw * P;
+    const uint64_t per = (uint64_t)Bw * (uint64_t)walk_pairs_per_walk(L, W);
     if (mode == 1 && per % batch != 0) return 1;
     or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
     int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
     int32_t *pv = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
-    int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
     const uint64_t end = first + count;
     int rc = 0;
     for (uint64_t s = first; s < end && rc == 0;) {
         uint64_t b = s / per, b0 = b * per, b1 = b0 + per;
-        for (uint64_t j = 0; j < (uint64_t)Bw; j++) {
-            walk_vertices(&wk, b * (uint64_t)Bw + j, vert);
-            for (uint64_t p = 0; p < P; p++) {
-                int a, c;
-                walk_pair_positions(L, W, (int64_t)p, &a, &c);
-                pu[p * (uint64_t)Bw + j] = vert[a];
-                pv[p * (uint64_t)Bw + j] = vert[c];
-            }
-        }
+        fill_walk_batch(&wk, b, pu, pv);
         or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, pu, pv, b0};
         uint64_t stop = b1 < end ? b1 : end;
         rc = train_range(&g, &h, U, C, U1, s, stop - s, mode, batch);
         s = stop;
     }
-    free(pu); free(pv); free(vert);
+    free(pu); free(pv);
     return rc;
 }
 
@@ -759,19 +768,15 @@ static void write_row_bf16(double *X, int64_t r, const double *inc, int d, uint6
 /* SEQ mode with bfloat16 tables: or_train's mode 0 (the increments of a sample
  * from the rows before it, in binary64), each row of each order written back
  * through write_row_bf16 in the order vertex row, then context slots 0..K. */
-int or_train_bf16(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
-                  const uint64_t *ethr, const int32_t *ealias,
-                  const uint64_t *nthr, const int32_t *nalias,
-                  uint64_t seed, uint32_t graph_id,
-                  int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
-                  double *U, double *C, double *U1, uint64_t first, uint64_t count,
-                  uint64_t stream)
+static void train_range_bf16(const or_graph *gp, const or_hyper *hp, double *U, double *C, double *U1,
+                             uint64_t first, uint64_t count, uint64_t stream)
 {
-    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
-    if ((orders & 2) && (!U || !C)) return 1;
-    if ((orders & 1) && !U1) return 1;
-    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
-    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    const or_graph g = *gp;
+    const or_hyper h = *hp;
+    const int d = h.d, K = h.K, orders = h.orders;
+    const double eta0 = h.eta0;
+    const uint64_t T = h.T, seed = g.seed;
+    const uint32_t graph_id = g.graph_id;
     int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(K + 1));
     double *dA = (double *)malloc(sizeof(double) * (size_t)d);
     double *dB = (double *)malloc(sizeof(double) * (size_t)d * (size_t)(K + 1));
@@ -790,6 +795,54 @@ int or_train_bf16(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
         }
     }
     free(ids); free(dA); free(dB);
+}
+
+int or_train_bf16(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const uint64_t *nthr, const int32_t *nalias,
+                  uint64_t seed, uint32_t graph_id,
+                  int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+                  double *U, double *C, double *U1, uint64_t first, uint64_t count,
+                  uint64_t stream)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, NULL, NULL, 0};
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    train_range_bf16(&g, &h, U, C, U1, first, count, stream);
+    return 0;
+}
+
+/* bfloat16 storage with the positive pairs of random walks (SEQ), as or_train_walk. */
+int or_train_bf16_walk(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                       const uint64_t *ethr, const int32_t *ealias,
+                       const uint64_t *nthr, const int32_t *nalias,
+                       const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                       int L, int W, int64_t Bw,
+                       uint64_t seed, uint32_t graph_id,
+                       int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+                       double *U, double *C, double *U1, uint64_t first, uint64_t count,
+                       uint64_t stream)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
+    if (!walker_ok(&wk)) return 1;
+    const uint64_t per = (uint64_t)Bw * (uint64_t)walk_pairs_per_walk(L, W);
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    int32_t *pv = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    const uint64_t end = first + count;
+    for (uint64_t s = first; s < end;) {
+        uint64_t b = s / per, b0 = b * per, stop = b0 + per < end ? b0 + per : end;
+        fill_walk_batch(&wk, b, pu, pv);
+        or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, pu, pv, b0};
+        train_range_bf16(&g, &h, U, C, U1, s, stop - s, stream);
+        s = stop;
+    }
+    free(pu); free(pv);
     return 0;
 }
 

@@ -122,37 +122,44 @@ def run_mid(out: str, walks: bool = False):
 
 
 def _sbm_run(args):
-    pairs, train_seed = args
+    pairs, storage, train_seed = args
     from synth.labels import node_classification_f1, sbm_workload
     g, labels, c = sbm_workload()
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
-    m = oracle.Model(tb, d=c["d"], K=c["K"], orders=c["orders"], T=c["T"], seed=train_seed, eta0=c["eta0"])
+    m = oracle.Model(tb, d=c["d"], K=c["K"], orders=c["orders"], T=c["T"], seed=train_seed, eta0=c["eta0"],
+                     storage=storage)
     m.train(0, c["T"], "seq", walks=oracle.WalkGraph(tb, **WALK) if pairs == "walks" else None)
-    return pairs, train_seed, node_classification_f1(m.U, labels, c["split_seed"])
+    return pairs, storage, train_seed, node_classification_f1(m.U, labels, c["split_seed"])
 
 
 def run_sbm_f1(out: str):
     """Node-classification Micro/Macro-F1 (Sec. V-A) of the labelled workload's vertex
-    embeddings U, trained by the oracle (SEQ, binary64) with arc-draw pairs and with
-    random-walk pairs; the workload's training seed, plus two more seeds whose spread
-    sizes the tolerance of the GPU comparison."""
+    embeddings U, trained by the oracle (SEQ) with arc-draw pairs and with random-walk
+    pairs, with binary64 tables and with bfloat16 table storage (the precision
+    extension's reference); the workload's training seed, plus two more seeds whose
+    spread sizes the tolerance of the GPU comparison."""
     from concurrent.futures import ProcessPoolExecutor
     from synth.labels import SBM, sbm_workload
     t0 = time.time()
     g, _, c = sbm_workload()
     seeds = [c["train_seed"], 70, 71]
-    jobs = [(p, s) for p in ("arcs", "walks") for s in seeds]
-    with ProcessPoolExecutor(max_workers=len(jobs)) as ex:
+    jobs = [(p, st, s) for st in ("binary64", "bf16") for p in ("arcs", "walks") for s in seeds]
+    with ProcessPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
         results = list(ex.map(_sbm_run, jobs))
     res = {"workload": "synth.labels.SBM", "config": SBM, "n": g.n, "m": g.m, "T": c["T"], "mode": "seq",
-           "precision": "binary64", "walk": WALK, "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
-    for pairs in ("arcs", "walks"):
-        rows = {s: f for p, s, f in results if p == pairs}
-        mi = [rows[s][0] for s in seeds]
-        ma = [rows[s][1] for s in seeds]
-        res[pairs] = {"micro": rows[c["train_seed"]][0], "macro": rows[c["train_seed"]][1],
-                      "micro_by_seed": dict(zip(map(str, seeds), mi)), "macro_by_seed": dict(zip(map(str, seeds), ma)),
-                      "sd_micro": float(np.std(mi, ddof=1)), "sd_macro": float(np.std(ma, ddof=1))}
+           "precision": "binary64 arithmetic; binary64 tables (arcs, walks) or bfloat16 tables (arcs_bf16, "
+                        "walks_bf16: nearest-rounded initial values, stochastically rounded writes)",
+           "walk": WALK, "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    for storage in ("binary64", "bf16"):
+        for pairs in ("arcs", "walks"):
+            rows = {s: f for p, st, s, f in results if p == pairs and st == storage}
+            mi = [rows[s][0] for s in seeds]
+            ma = [rows[s][1] for s in seeds]
+            key = pairs if storage == "binary64" else pairs + "_bf16"
+            res[key] = {"micro": rows[c["train_seed"]][0], "macro": rows[c["train_seed"]][1],
+                        "micro_by_seed": dict(zip(map(str, seeds), mi)),
+                        "macro_by_seed": dict(zip(map(str, seeds), ma)),
+                        "sd_micro": float(np.std(mi, ddof=1)), "sd_macro": float(np.std(ma, ddof=1))}
     res["oracle_seconds"] = round(time.time() - t0, 1)
     with open(os.path.join(HERE, out), "w") as f:
         json.dump(res, f, indent=1)

@@ -296,6 +296,50 @@ def test_one_walk_sample_applies_the_per_sample_rule(s, orders):
             assert np.array_equal(X, ref[k]), k
 
 
+def _bf16_neighbours(x):
+    f = np.float32(x)
+    b = f.view(np.uint32)
+    lo = np.uint32(b & np.uint32(0xFFFF0000)).view(np.float32)
+    if np.uint32(b & np.uint32(0xFFFF)) == 0:
+        return float(lo), float(lo)
+    hi = np.uint32((b & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32)
+    return float(lo), float(hi)
+
+
+@pytest.mark.parametrize("s", [0, 77, 500])
+def test_one_bf16_walk_sample_lands_next_to_the_binary64_step(s):
+    """bfloat16 storage with walk pairs: one sample writes exactly the rows of its walk
+    pair and negatives, each element once written on a bfloat16 neighbour of the binary64
+    step from the same tables; a zero step leaves the tables as they were."""
+    g = _graph(12, 40, 160, zero_frac=0.0)
+    t, wg = _walker(g, L=8, W=2, Bw=4)
+    K = 2
+    a = oracle.Model(t, d=16, K=K, orders=2, T=1000, seed=3, eta0=0.5, storage="bf16")
+    b = oracle.Model(t, d=16, K=K, orders=2, T=1000, seed=3, eta0=0.5)
+    rng = np.random.default_rng(s)
+    for X, Y in ((a.U, b.U), (a.C, b.C)):
+        X[:] = oracle.bf16_rne(rng.normal(0, 0.3, size=X.shape))
+        Y[:] = X
+    before = (a.U.copy(), a.C.copy())
+    a.train(s, 1, "seq", walks=wg)
+    b.train(s, 1, "seq", walks=wg)
+    u, v = wg.pairs(seed=3, graph_id=0, first=s, count=1)
+    neg = oracle.sample_negatives(g.n, t.nthr, t.nalias, seed=3, graph_id=0, K=K, first=s, count=1)[0]
+    ids = [int(v[0])] + [int(x) for x in neg]
+    for X, Y, X0, rows in ((a.U, b.U, before[0], [int(u[0])]), (a.C, b.C, before[1], ids)):
+        untouched = np.setdiff1d(np.arange(X.shape[0]), rows)
+        assert np.array_equal(X[untouched], X0[untouched])
+        for r in set(rows):
+            if rows.count(r) != 1:
+                continue
+            for c in range(X.shape[1]):
+                assert X[r, c] in _bf16_neighbours(Y[r, c]), (r, c)
+    z = oracle.Model(t, d=16, K=K, orders=2, T=1000, seed=3, eta0=0.0, storage="bf16")
+    z0 = (z.U.copy(), z.C.copy())
+    z.train(0, 300, "seq", walks=wg)
+    assert np.array_equal(z.U, z0[0]) and np.array_equal(z.C, z0[1])
+
+
 def test_walk_snapshot_with_batch_one_is_seq():
     g = _graph(10, 120, 600, zero_frac=0.0)
     t, wg = _walker(g, L=10, W=2, Bw=16)
