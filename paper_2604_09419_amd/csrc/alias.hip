@@ -378,6 +378,7 @@ lh_status build_alias(lh_handle *h, void *scratch, size_t bytes)
     if (!scratch) return fail(h, LH_ERR_INVALID_ARG, "scratch is NULL");
     if (bytes < L.total) return fail(h, LH_ERR_WORKSPACE_TOO_SMALL, "alias scratch too small");
     h->edge_ready = h->neg_ready = false;
+    h->walk.loaded = -1;  // walk roots come from the edge table: pairs made before are stale
     // Out- and in-degrees, the negative weights' canonical scan (for W_nu), and the
     // heat of every node, before either table's records are written.
     {
@@ -450,6 +451,7 @@ __global__ void k_export(const EdgeRec *erec, const NegRec *nrec, long long N, u
 
 lh_status import_alias(lh_handle *h, int which, const uint64_t *thr, const int32_t *alias)
 {
+    if (which == LH_ALIAS_EDGE) h->walk.loaded = -1;  // walk roots come from this table
     long long N = which == LH_ALIAS_EDGE ? h->m : h->n;
     RecOut o{which == LH_ALIAS_EDGE ? h->erec : nullptr, which == LH_ALIAS_EDGE ? nullptr : h->nrec,
              h->src, h->dst, nullptr};

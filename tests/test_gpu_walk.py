@@ -133,6 +133,31 @@ def test_walk_pairs_across_buffer_fills():
     tr.close()
 
 
+def test_walk_pairs_follow_an_imported_edge_table():
+    """Walk roots come from the edge table: after lh_import_alias of another edge table,
+    the pairs (already generated for the old one) are made again from the new one."""
+    import copy
+    lh = _lh()
+    g, _, _, _ = config_graph("C1")
+    t, wg = _oracle_walk(g, 30, 2, 64)
+    tr = trainer_for(g, d=8, K=1, orders=2, seed=6, total_samples=10, init=False)
+    tr.build_walks(walk_length=30, window=2, walks_per_batch=64)
+    u0, _ = tr.walk_pairs(0, 5000)
+    ou0, _ = wg.pairs(seed=6, graph_id=0, first=0, count=5000)
+    assert np.array_equal(u0.cpu().numpy(), ou0)
+    rng = np.random.default_rng(1)
+    t2 = oracle.Tables(g.n, g.src, g.dst, rng.lognormal(0, 2.0, size=g.m).astype(np.float32))
+    tr.import_alias(lh.LH_ALIAS_EDGE, t2.ethr, t2.ealias)
+    wg2 = copy.copy(wg)
+    wg2.t = copy.copy(t)
+    wg2.t.ethr, wg2.t.ealias = t2.ethr, t2.ealias
+    u1, v1 = tr.walk_pairs(0, 5000)
+    ou1, ov1 = wg2.pairs(seed=6, graph_id=0, first=0, count=5000)
+    assert not np.array_equal(ou1, ou0)
+    assert np.array_equal(u1.cpu().numpy(), ou1) and np.array_equal(v1.cpu().numpy(), ov1)
+    tr.close()
+
+
 def test_detach_returns_to_arc_draws():
     g, _, _, _ = config_graph("C1")
     t = oracle.Tables(g.n, g.src, g.dst, g.w)
