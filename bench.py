@@ -16,7 +16,7 @@ with bfloat16 tables (C3) for the BF16-over-FP32 speedup, and the held-out AUC o
 is compared with the binary64 oracle's.  The C3 embedding error is measured on the first
 2^20 samples in SNAPSHOT mode against the oracle's binary64 SNAPSHOT run.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -263,7 +263,7 @@ def held_out_auc(tr, hs, hd, neg, orders):
 
 def host_threads():
     """Threads for the oracle's CPU legs: every core in this process's affinity mask, or
-    fewer when OMP_NUM_THREADS says so (a GPU machine gives one GPU's job a fixed share of
+    fewer when OMP_NUM_THREADS says so (a shared host can give one GPU's job a fixed share of
     its cores that way).  Returns (threads, affinity core count, reason for a cap)."""
     cores = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS", "")
@@ -565,7 +565,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the sharded design is described, not built).", file=sys.stderr)
         sys.exit(2)
 

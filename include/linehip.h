@@ -55,7 +55,7 @@ typedef enum {
     LH_ERR_ZERO_WEIGHT = 3,      /* device-detected: NaN/negative weight or zero total */
     LH_ERR_WORKSPACE_TOO_SMALL = 4,
     LH_ERR_NOT_BUILT = 5,        /* a call needs lh_bind / lh_set_graph / alias first   */
-    LH_ERR_UNSUPPORTED = 6,      /* a parameter combination this build has no kernel for */
+    LH_ERR_UNSUPPORTED = 6,      /* a parameter combination the library has no kernel for */
     LH_ERR_NO_DEVICE = 7,        /* no HIP device, or the device index is out of range  */
     LH_ERR_HIP = 8               /* a HIP runtime call failed; see lh_last_error       */
 } lh_status;
