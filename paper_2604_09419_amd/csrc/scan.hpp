@@ -66,6 +66,36 @@ struct OpAdd {
     __device__ static I combine(I off, I loc) { return off + loc; }
 };
 
+// Elements a chain loads ahead of its arithmetic: the chain itself is one dependent
+// sequence, but its loads are not, so they are issued in blocks of this many.
+constexpr int CHAIN_BLOCK = 16;
+
+// The left-to-right chain of one chunk [lo, hi), in place or not (each block is loaded
+// before any of its results is stored).
+template <class Op>
+__device__ __forceinline__ typename Op::T chain(const typename Op::T *x, typename Op::T *out, long long lo,
+                                                long long hi)
+{
+    typename Op::State st = Op::init();
+    typename Op::T last{};
+    long long i = lo;
+    for (; i + CHAIN_BLOCK <= hi; i += CHAIN_BLOCK) {
+        typename Op::T v[CHAIN_BLOCK];
+#pragma unroll
+        for (int k = 0; k < CHAIN_BLOCK; ++k) v[k] = x[i + k];
+#pragma unroll
+        for (int k = 0; k < CHAIN_BLOCK; ++k) {
+            last = Op::step(st, v[k]);
+            out[i + k] = last;
+        }
+    }
+    for (; i < hi; ++i) {
+        last = Op::step(st, x[i]);
+        out[i] = last;
+    }
+    return last;
+}
+
 template <class Op>
 __global__ void __launch_bounds__(256) k_chunk_chain(const typename Op::T *x, typename Op::T *out,
                                                      long long n, typename Op::T *tot)
@@ -74,13 +104,7 @@ __global__ void __launch_bounds__(256) k_chunk_chain(const typename Op::T *x, ty
     long long nch = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
     if (c >= nch) return;
     long long lo = c * SCAN_CHUNK, hi = lo + SCAN_CHUNK < n ? lo + SCAN_CHUNK : n;
-    typename Op::State st = Op::init();
-    typename Op::T last{};
-    for (long long i = lo; i < hi; ++i) {
-        last = Op::step(st, x[i]);
-        out[i] = last;
-    }
-    tot[c] = last;
+    tot[c] = chain<Op>(x, out, lo, hi);
 }
 
 template <class Op>

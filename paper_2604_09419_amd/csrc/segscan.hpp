@@ -75,13 +75,7 @@ __global__ void __launch_bounds__(256) k_seg_chain(typename Op::T *x, const long
 {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
-    typename Op::State st = Op::init();
-    typename Op::T last{};
-    for (long long i = cstart[c]; i < cend[c]; ++i) {
-        last = Op::step(st, x[i]);
-        x[i] = last;
-    }
-    tot[c] = last;
+    tot[c] = chain<Op>(x, x, cstart[c], cend[c]);
 }
 
 // Listed chunks c (j > 0): element i becomes combine(inc[c - 1], loc[i]), with inc the
