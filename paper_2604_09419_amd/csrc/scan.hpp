@@ -68,7 +68,7 @@ struct OpAdd {
 
 // Elements a chain loads ahead of its arithmetic: the chain itself is one dependent
 // sequence, but its loads are not, so they are issued in blocks of this many.
-constexpr int CHAIN_BLOCK = 16;
+constexpr int CHAIN_BLOCK = 64;
 
 // The left-to-right chain of one chunk [lo, hi), in place or not (each block is loaded
 // before any of its results is stored).
