@@ -496,6 +496,12 @@ def bench_large(args):
     tb = time.time()
     tr.build_alias()
     build_s = time.time() - tb
+    walk_s = None
+    if args.walks:
+        tw = time.time()
+        tr.build_walks(**WALK)
+        walk_s = time.time() - tw
+        log(f"[bench] {name} walk rows built in {walk_s:.2f}s")
     tr.init_embeddings()
     tr.train_steps(0, T)
     ms = tr.last_train_ms()
@@ -513,13 +519,15 @@ def bench_large(args):
         cpu = cpu_baseline(dict(cfg, T=T), host_graph, cfg["seed"], label=f"{name} workload")
         log(f"[bench] cpu baseline {cpu['value']:.3e} samples/s")
     out = {
-        "metric": f"edge samples/sec at d=128,K=5 ({name}, bf16)", "value": T / (ms * 1e-3),
+        "metric": f"edge samples/sec at d=128,K=5 ({name}, bf16{', random-walk pairs' if args.walks else ''})",
+        "value": T / (ms * 1e-3),
         "unit": "edge samples/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "table_dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"{name}: {graph}, 67108864 nodes, 2^30 arcs, d=128, K=5, second order, "
                                "bf16 tables", "T": T,
-                   "kernel_config": kcfg, "alias_build_s": build_s, "hot_shadow": args.hot_shadow},
+                   "kernel_config": kcfg, "alias_build_s": build_s, "hot_shadow": args.hot_shadow,
+                   "pairs": f"random walks {WALK}, walk rows built in {walk_s:.2f} s" if args.walks else "arc draws"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_hogwild (bf16, order 2)",
                      "bytes_per_sample": bps},
@@ -546,6 +554,8 @@ def main():
     ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
     ap.add_argument("--no-walks", action="store_true", help="skip the random-walk pair legs")
     ap.add_argument("--no-f1", action="store_true", help="skip the node-classification leg")
+    ap.add_argument("--walks", action="store_true",
+                    help="C5 and C5U: positive pairs from random walks (the training call includes the walks)")
     ap.add_argument("--hot-shadow", action="store_true",
                     help="bfloat16 runs: hot rows accumulate in a binary32 shadow per launch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2604_09419_amd", "tune_cache.json"))
