@@ -95,6 +95,15 @@ def lib():
             L.or_train_bf16_walk.argtypes = [P, P, i64, i64, P, P, P, P, P, P, P, P, i32, i32, i64, u64,
                                              u32, i32, i32, i32, f64, f64, f64, u64, P, P, P, u64, u64, u64]
             L.or_train_bf16_walk.restype = i32
+            L.or_pool_size.argtypes = [u64]
+            L.or_pool_size.restype = u64
+            L.or_pool_pairs.argtypes = [i64, i64, P, P, P, P, P, P, P, P, u64, u32, i32, i32, i64, u64,
+                                        P, P, u64, u64, P, P]
+            L.or_pool_pairs.restype = i32
+            L.or_train_pool.argtypes = [P, P, i64, i64, P, P, P, P, P, P, P, P, i32, i32, i64, u64, u64,
+                                        u32, i32, i32, i32, f64, f64, f64, u64, P, P, P, u64, u64, i32,
+                                        u64, i64]
+            L.or_train_pool.restype = i32
         _lib = L
     return _lib
 
@@ -239,12 +248,31 @@ class WalkGraph:
             raise ValueError("or_walk_pairs rejected its arguments")
         return u, v
 
+    def pool(self, seed: int, graph_id: int, R: int, first: int = 0, count: int = 0):
+        """The pair pool of R collected walk pairs (Sec. IV-C, Augmented-Pair): returns
+        (pool_u, pool_v, u, v), the collected pairs and the positive pairs samples
+        [first, first + count) draw from them."""
+        pu = np.zeros(R, dtype=np.int32)
+        pv = np.zeros(R, dtype=np.int32)
+        u = np.zeros(max(count, 1), dtype=np.int32)
+        v = np.zeros(max(count, 1), dtype=np.int32)
+        if lib().or_pool_pairs(*self._args(), seed, graph_id, self.L, self.W, self.Bw, R, _p(pu), _p(pv),
+                               first, count, _p(u), _p(v)) != 0:
+            raise ValueError("or_pool_pairs rejected its arguments")
+        return pu, pv, u[:count], v[:count]
+
     def walks(self, seed: int, graph_id: int, k0: int, nwalks: int) -> np.ndarray:
         """Vertices of walks k0 .. k0 + nwalks - 1, [nwalks, L]."""
         out = np.zeros((nwalks, self.L), dtype=np.int32)
         if lib().or_walk_vertices(*self._args(), seed, graph_id, self.L, k0, nwalks, _p(out)) != 0:
             raise ValueError("or_walk_vertices rejected its arguments")
         return out
+
+
+def pool_size(T: int) -> int:
+    """Pairs a pool collects for a run of T samples: the least R >= 2 with
+    R (R - 1) / 2 >= T (about sqrt(2 T), Sec. IV-C)."""
+    return int(lib().or_pool_size(T))
 
 
 def sample(t: Tables, seed: int, graph_id: int, K: int, first: int, count: int):
@@ -320,10 +348,27 @@ class Model:
                     lib().or_bf16_rne(_p(X), X.size)
 
     def train(self, first: int, count: int, mode: str = "seq", batch: int = 0,
-              walks: Optional["WalkGraph"] = None):
+              walks: Optional["WalkGraph"] = None, pool: int = 0):
         """SEQ (each sample applied at once) or SNAPSHOT (Eq. (4) per batch).  ``walks``:
-        positive pairs from that random-walk source instead of arc draws."""
+        positive pairs from that random-walk source instead of arc draws; with ``pool`` = R
+        > 0, from the pair pool of R pairs collected from it (Sec. IV-C, Augmented-Pair)."""
         t = self.t
+        if pool:
+            if walks is None:
+                raise ValueError("a pair pool is collected from a walk source")
+            if self.storage == "bf16" and mode != "seq":
+                raise ValueError("bfloat16 storage is modelled in SEQ mode only")
+            wg = walks
+            rc = lib().or_train_pool(_p(t.src), _p(t.dst), t.n, t.m, _p(t.ethr), _p(t.ealias),
+                                     _p(t.nthr), _p(t.nalias), _p(wg.off), _p(wg.nbr), _p(wg.thr),
+                                     _p(wg.alias), wg.L, wg.W, wg.Bw, int(pool), self.seed, self.graph_id,
+                                     self.d, self.K, self.orders, self.eta0, self.lam, self.alpha, self.T,
+                                     _p(self.U), _p(self.C), _p(self.U1), first, count,
+                                     0 if mode == "seq" else 1, batch,
+                                     self.sr_stream if self.storage == "bf16" else -1)
+            if rc != 0:
+                raise ValueError("or_train_pool rejected its arguments")
+            return
         if walks is not None and self.storage == "bf16":
             if mode != "seq":
                 raise ValueError("bfloat16 storage is modelled in SEQ mode only")

@@ -19,6 +19,8 @@
  *     the weight-normalised edge distribution.
  *   - Algorithms 2-3 (RandomWalk, GeneratePairs), Sec. IV-B: positive pairs from random
  *     walks rooted at such an edge (the walk pair source below).
+ *   - Sec. IV-C (variants of random walks), Augmented-Pair: a pool of walk pairs
+ *     collected before training and expanded by recombination (the pair pool below).
  *   - Sec. V-A (NOMAD hyperparameters): single-precision SGD, eta = 0.025.
  *
  * Floating point: everything here is IEEE binary64 except the Hogwild timing mode,
@@ -844,6 +846,127 @@ int or_train_bf16_walk(const int32_t *src, const int32_t *dst, int64_t n, int64_
     }
     free(pu); free(pv);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* A pre-generated pair pool (Sec. IV-C, the Augmented-Pair variant): walks    */
+/* are run before training only until about sqrt(2 T) pairs are collected, and */
+/* the training pairs are combinations of the collected ones.                  */
+/*   Collected pairs: the first R pairs of the walk source in its sample order */
+/*   (samples 0 .. R-1 above), (u_r, v_r).  R for a run of T samples is the     */
+/*   least R >= 2 with R (R - 1) / 2 >= T (or_pool_size).                       */
+/*   Expansion: the R^2 combinations (u_i, v_j) of one collected pair's first   */
+/*   vertex with any collected pair's second vertex; i = j gives the collected  */
+/*   pairs back, i != j the recombined ones (mostly not arcs of the graph).     */
+/*   Sample s draws its positive pair from the expansion uniformly: with x0, x1 */
+/*   the first two words of the Philox block an arc draw of sample s uses (key  */
+/*   (seed, graph_id), counter (s, 0, 0, 0)), i = floor(x0 R / 2^64) and        */
+/*   j = floor(x1 R / 2^64).  The negatives are drawn as for any sample.         */
+/* ------------------------------------------------------------------------- */
+uint64_t or_pool_size(uint64_t T)
+{
+    uint64_t R = 2;
+    while ((u128)R * (u128)(R - 1) / 2 < (u128)T) R++;
+    return R;
+}
+
+/* The R collected pairs: pu/pv[r] = the walk source's pair of sample r. */
+static int pool_collect(const or_walker *wk, uint64_t R, int32_t *pu, int32_t *pv)
+{
+    const uint64_t per = (uint64_t)wk->Bw * (uint64_t)walk_pairs_per_walk(wk->L, wk->W);
+    int32_t *bu = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    int32_t *bv = (int32_t *)malloc(sizeof(int32_t) * (size_t)per);
+    if (!bu || !bv) { free(bu); free(bv); return 1; }
+    for (uint64_t b = 0; b * per < R; b++) {
+        fill_walk_batch(wk, b, bu, bv);
+        for (uint64_t i = 0; i < per && b * per + i < R; i++) {
+            pu[b * per + i] = bu[i];
+            pv[b * per + i] = bv[i];
+        }
+    }
+    free(bu); free(bv);
+    return 0;
+}
+
+static void pool_pair(const uint64_t *seed_gid, const int32_t *pu, const int32_t *pv, uint64_t R, uint64_t s,
+                      int32_t *u, int32_t *v)
+{
+    uint64_t ctr[4] = {s, 0, 0, 0}, x[4];
+    or_philox4x64_10(seed_gid[0], seed_gid[1], ctr, x);
+    uint64_t i = (uint64_t)(((u128)x[0] * R) >> 64), j = (uint64_t)(((u128)x[1] * R) >> 64);
+    *u = pu[i];
+    *v = pv[j];
+}
+
+/* The collected pairs (pool_u/pool_v, R each) and the positive pairs of samples
+ * [first, first + count) drawn from the pool of R pairs (u, v: count each; either pair of
+ * outputs may be NULL). */
+int or_pool_pairs(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                  uint64_t seed, uint32_t graph_id, int L, int W, int64_t Bw, uint64_t R,
+                  int32_t *pool_u, int32_t *pool_v, uint64_t first, uint64_t count, int32_t *u, int32_t *v)
+{
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
+    if (!walker_ok(&wk) || R < 1) return 1;
+    int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    int32_t *pv = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    if (!pu || !pv || pool_collect(&wk, R, pu, pv) != 0) { free(pu); free(pv); return 1; }
+    if (pool_u && pool_v)
+        for (uint64_t r = 0; r < R; r++) { pool_u[r] = pu[r]; pool_v[r] = pv[r]; }
+    const uint64_t key[2] = {seed, (uint64_t)graph_id};
+    if (u && v)
+        for (uint64_t i = 0; i < count; i++) pool_pair(key, pu, pv, R, first + i, &u[i], &v[i]);
+    free(pu); free(pv);
+    return 0;
+}
+
+/* Training (or_train, or with bf16_stream >= 0 the bfloat16-storage SEQ run of
+ * or_train_bf16 with that rounding stream) with positive pairs drawn from the pool of R
+ * pairs.  SNAPSHOT batches may fall anywhere: the pairs of a range do not depend on how
+ * it is cut. */
+int or_train_pool(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                  const uint64_t *ethr, const int32_t *ealias,
+                  const uint64_t *nthr, const int32_t *nalias,
+                  const int64_t *off, const int32_t *nbr, const uint64_t *wthr, const int32_t *walias,
+                  int L, int W, int64_t Bw, uint64_t R,
+                  uint64_t seed, uint32_t graph_id,
+                  int d, int K, int orders, double eta0, double lambda, double alpha, uint64_t T,
+                  double *U, double *C, double *U1,
+                  uint64_t first, uint64_t count, int mode, uint64_t batch, int64_t bf16_stream)
+{
+    if (d <= 0 || K < 0 || T == 0 || (orders & 3) == 0) return 1;
+    if ((orders & 2) && (!U || !C)) return 1;
+    if ((orders & 1) && !U1) return 1;
+    if (mode == 1 && batch == 0) return 1;
+    if (bf16_stream >= 0 && mode != 0) return 1;
+    or_walker wk = {n, m, src, dst, ethr, ealias, off, nbr, wthr, walias, seed, graph_id, L, W, Bw};
+    if (!walker_ok(&wk) || R < 1) return 1;
+    int32_t *cu = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    int32_t *cv = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    if (!cu || !cv || pool_collect(&wk, R, cu, cv) != 0) { free(cu); free(cv); return 1; }
+    /* A SNAPSHOT batch must see all of its pairs at once: pieces are whole batches. */
+    uint64_t piece = (uint64_t)1 << 20;
+    if (mode == 1) piece = batch > piece ? batch : (piece / batch) * batch;
+    int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)piece);
+    int32_t *pv = (int32_t *)malloc(sizeof(int32_t) * (size_t)piece);
+    const uint64_t key[2] = {seed, (uint64_t)graph_id};
+    or_hyper h = {d, K, orders, eta0, lambda, alpha, T};
+    int rc = (!pu || !pv) ? 1 : 0;
+    const uint64_t end = first + count;
+    for (uint64_t s = first; s < end && rc == 0;) {
+        /* pieces start at multiples of `piece` (so at batch starts) */
+        uint64_t p0 = (s / piece) * piece, stop = p0 + piece < end ? p0 + piece : end;
+        for (uint64_t t = p0; t < stop; t++) pool_pair(key, cu, cv, R, t, &pu[t - p0], &pv[t - p0]);
+        or_graph g = {n, m, src, dst, ethr, ealias, nthr, nalias, seed, graph_id, K, pu, pv, p0};
+        if (bf16_stream >= 0)
+            train_range_bf16(&g, &h, U, C, U1, s, stop - s, (uint64_t)bf16_stream);
+        else
+            rc = train_range(&g, &h, U, C, U1, s, stop - s, mode, batch);
+        s = stop;
+    }
+    free(cu); free(cv); free(pu); free(pv);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */
