@@ -329,6 +329,33 @@ LH_API lh_status lh_walk_pairs(lh_handle *h, uint64_t first, uint64_t count, int
  * Synchronises the stream.  LH_ERR_NOT_BUILT before lh_walk_build. */
 LH_API lh_status lh_walk_export(lh_handle *h, int64_t *offsets, uint64_t *thr, int32_t *keep, int32_t *alias);
 
+/* ---- A pre-generated pair pool (Sec. IV-C, the Augmented-Pair variant: walks run before
+ * training only until about sqrt(2 T) pairs are collected, and the training pairs are
+ * enumerated combinations of them, so sampling is decoupled from training).
+ *
+ * The pool's R collected pairs are the walk source's first R pairs (samples 0 .. R - 1
+ * above), (u_r, v_r).  Its expansion is the R^2 combinations (u_i, v_j): i = j gives a
+ * collected pair back, i != j a recombined one (mostly not an arc of the graph).  Sample
+ * s draws its positive pair from the expansion uniformly with the Philox4x64-10 block an
+ * arc draw of sample s would use (key (seed, graph_id), counter (s, 0, 0, 0)): with x0, x1
+ * its first two words, i = floor(x0 R / 2^64) and j = floor(x1 R / 2^64).  Its K
+ * negatives are drawn as before.
+ *
+ * lh_walk_pool_size: *pairs = the pool size for a run of total_samples samples, the least
+ * R >= 2 with R (R - 1) / 2 >= total_samples.  Host-only.  LH_ERR_INVALID_ARG for a NULL
+ * output or total_samples = 0. */
+LH_API lh_status lh_walk_pool_size(uint64_t total_samples, uint64_t *pairs);
+
+/* Switch the handle's positive pairs to a pool of `pairs` = R collected pairs (R >= 1;
+ * 0 switches back to the walk pairs).  lh_train_steps (both modes) and lh_sample then
+ * take their pairs from the pool.  The pool lives in the walk pair buffer (its first
+ * fill, generated now on the handle's stream if it is not there); R may not exceed that
+ * buffer's pairs (LH_ERR_OUT_OF_RANGE: about 2^24, enough for total_samples up to about
+ * 1.4 10^14).  Enqueued.  LH_ERR_NOT_BUILT before lh_walk_build.  While a pool is on,
+ * lh_walk_pairs returns LH_ERR_UNSUPPORTED (lh_sample gives the pool's pairs);
+ * lh_walk_build and lh_walk_detach end the pool. */
+LH_API lh_status lh_walk_pool(lh_handle *h, uint64_t pairs);
+
 /* Number of exported entry points (for load checks) and their names. */
 LH_API int lh_abi_symbol_count(void);
 LH_API const char *lh_abi_symbol_name(int i);

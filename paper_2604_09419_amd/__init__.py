@@ -141,6 +141,20 @@ class Trainer:
     def detach_walks(self):
         _lib.lh_walk_detach(self.h)
 
+    def build_pool(self, pairs: int = 0):
+        """Draw the positive pairs from a pool of walk pairs collected up front (Sec. IV-C,
+        Augmented-Pair): ``pairs`` = R collected pairs, by default the library's size for
+        this handle's total_samples (about sqrt(2 T)).  Needs build_walks first."""
+        R = int(pairs) if pairs else _lib.lh_walk_pool_size(self.T)
+        _lib.lh_walk_pool(self.h, R)
+        self.pool_pairs = R
+        return R
+
+    def drop_pool(self):
+        """Back to the walk pairs."""
+        _lib.lh_walk_pool(self.h, 0)
+        self.pool_pairs = 0
+
     def import_alias(self, which: int, thr, alias):
         torch = self.torch
         self._after_caller()

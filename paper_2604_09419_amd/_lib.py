@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
         "lh_walk_pairs": [P, u64, u64, P, P],
         "lh_walk_export": [P, P, P, P, P],
         "lh_walk_detach": [P],
+        "lh_walk_pool_size": [u64, ctypes.POINTER(u64)],
+        "lh_walk_pool": [P, u64],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -290,6 +292,16 @@ def lh_walk_export(h, off_ptr: int, thr_ptr: int, keep_ptr: int, alias_ptr: int)
 
 def lh_walk_detach(h):
     check(lib().lh_walk_detach(h), "lh_walk_detach", h)
+
+
+def lh_walk_pool_size(total_samples: int) -> int:
+    pairs = ctypes.c_uint64()
+    check(lib().lh_walk_pool_size(total_samples, ctypes.byref(pairs)), "lh_walk_pool_size")
+    return pairs.value
+
+
+def lh_walk_pool(h, pairs: int):
+    check(lib().lh_walk_pool(h, pairs), "lh_walk_pool", h)
 
 
 def lh_abi_symbols():

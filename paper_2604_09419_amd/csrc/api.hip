@@ -55,6 +55,7 @@ GraphDev graph_dev(const lh_handle *h)
     g.pairs = nullptr;
     g.pairs_first = 0;
     g.heat = h->ws ? (const uint8_t *)(h->ws + h->lay.nheat) : nullptr;
+    g.pool_n = 0;
     return g;
 }
 
@@ -123,6 +124,7 @@ static const char *const kSymbols[] = {
     "lh_status_string",   "lh_last_error",     "lh_destroy",       "lh_batch_create",    "lh_batch_tune",
     "lh_batch_capture",   "lh_batch_launch",   "lh_batch_run",     "lh_batch_last_ms",   "lh_batch_config",    "lh_batch_done",      "lh_batch_destroy",
     "lh_walk_size",       "lh_walk_build",     "lh_walk_pairs",    "lh_walk_export",     "lh_walk_detach",
+    "lh_walk_pool_size",  "lh_walk_pool",
     "lh_abi_symbol_count", "lh_abi_symbol_name",
 };
 
@@ -333,6 +335,7 @@ lh_status lh_train_steps(lh_handle *h, uint64_t first, uint64_t count)
             GraphDev gd = graph_dev(h);
             gd.pairs = pairs;
             gd.pairs_first = pf;
+            gd.pool_n = pairs ? h->walk.pool : 0;
             hipError_t le = launch_hogwild(gd, h->p.dtype, h->p.orders, h->cfg, sf, sf + sc, h->num_cu,
                                            shadowed ? &shc : nullptr, h->stream);
             return le == hipSuccess ? LH_OK : hip_fail(h, le, "hogwild launch");

@@ -42,6 +42,10 @@ struct GraphDev {
     const int2 *pairs;
     unsigned long long pairs_first;
     const uint8_t *heat;
+    // With pairs set and pool_n = R > 0: a pair pool instead, pairs[0 .. R) the collected
+    // pairs, and sample s takes (pairs[i].x, pairs[j].y) with i, j slot 0's two column
+    // draws over R.
+    unsigned long long pool_n;
 };
 
 // The random-walk pair source of a handle (lh_walk_build).
@@ -54,6 +58,7 @@ struct WalkState {
     WalkRec *rec = nullptr;           // [2m] row entries
     int2 *pairs = nullptr;            // [chunk_walks * P]
     long long loaded = -1;            // the chunk the buffer holds (-1: none)
+    unsigned long long pool = 0;      // pair pool: its R collected pairs (chunk 0's first R); 0: none
 };
 
 // Persistent walk memory: offsets, records, pair buffer (256-byte aligned pieces).

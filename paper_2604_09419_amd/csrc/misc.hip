@@ -200,9 +200,9 @@ __global__ void k_sample(GraphDev g, unsigned long long first, unsigned long lon
     unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const unsigned long long s = first + i;
-    const SlotDraw de = draw_slot(g, s, 0, g.m);
+    const SlotDraw de = draw_slot(g, s, 0, slot0_columns(g));
     uint4 r0, r1;
-    load_pair_rec(g, s, de.col, r0, r1);
+    load_pair_rec(g, s, de.col, de.x1, r0, r1);
     int uu = 0, vv = 0;
     (void)edge_pick(r0, r1, de.x1, uu, vv);
     u[i] = uu;
@@ -222,6 +222,7 @@ void launch_sample(lh_handle *h, unsigned long long first, unsigned long long co
     GraphDev g = graph_dev(h);
     g.pairs = pairs;
     g.pairs_first = pairs_first;
+    g.pool_n = pairs ? h->walk.pool : 0;
     if (count == 0) return;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)LH_CDIV(count, 256)), dim3(256), 0, h->stream, g, first, count, u,
                        v, neg);

@@ -181,6 +181,7 @@ lh_status train_snapshot(lh_handle *h, unsigned long long first, unsigned long l
     GraphDev g = graph_dev(h);
     g.pairs = pairs;
     g.pairs_first = pairs_first;
+    g.pool_n = pairs ? h->walk.pool : 0;
     hipStream_t s = h->stream;
     const unsigned long long B = (unsigned long long)p.batch;
     const int nord = p.orders == 3 ? 2 : 1;

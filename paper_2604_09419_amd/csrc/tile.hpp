@@ -90,18 +90,32 @@ __device__ __forceinline__ void load_edge_rec(const EdgeRec *erec, long long col
     r1 = er[1];
 }
 
+// Columns of slot 0's draw: the edge table's arcs, or the pair pool's collected pairs.
+__device__ __forceinline__ long long slot0_columns(const GraphDev &g)
+{
+    return g.pool_n ? (long long)g.pool_n : g.m;
+}
+
 // Slot 0's record words: the edge table's record of the drawn column (Algorithm 3's root
 // edge), or, when the positive pairs come from random walks, a record that yields the
 // sample's walk pair (u, v) whatever the threshold word (both outcomes are (u, v)), with
-// the heats of u and v in the record's heat word.
-__device__ __forceinline__ void load_pair_rec(const GraphDev &g, unsigned long long s, long long col, uint4 &r0,
-                                              uint4 &r1)
+// the heats of u and v in the record's heat word.  With a pair pool (Sec. IV-C,
+// Augmented-Pair) the pair is the first vertex of collected pair col (the first column
+// draw) and the second vertex of collected pair floor(x1 R / 2^64) (the second word).
+__device__ __forceinline__ void load_pair_rec(const GraphDev &g, unsigned long long s, long long col,
+                                              unsigned long long x1, uint4 &r0, uint4 &r1)
 {
     if (g.pairs == nullptr) {
         load_edge_rec(g.erec, col, r0, r1);
         return;
     }
-    const int2 p = g.pairs[s - g.pairs_first];
+    int2 p;
+    if (g.pool_n) {
+        p.x = g.pairs[col].x;
+        p.y = g.pairs[draw_column(x1, (long long)g.pool_n)].y;
+    } else {
+        p = g.pairs[s - g.pairs_first];
+    }
     const unsigned hu = g.heat[p.x], hv = g.heat[p.y];
     r0 = make_uint4(~0u, ~0u, 0u, (unsigned)p.x);
     r1 = make_uint4((unsigned)p.y, (unsigned)p.x, (unsigned)p.y, hu | (hv << 8) | (hu << 16) | (hv << 24));
@@ -555,9 +569,9 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
             // One Philox block at a time, its record load issued at once, so the loads of
             // all 1 + K slots are in flight together while the blocks are not interleaved
             // (which would hold 1 + K blocks of state in registers).
-            const SlotDraw de = draw_slot(g, s, 0, g.m);
+            const SlotDraw de = draw_slot(g, s, 0, slot0_columns(g));
             uint4 r0, r1;
-            load_pair_rec(g, s, de.col, r0, r1);
+            load_pair_rec(g, s, de.col, de.x1, r0, r1);
             my_sr = (uint32_t)de.x2;
             __builtin_amdgcn_sched_barrier(0);
             SlotDraw dn[KMAX];

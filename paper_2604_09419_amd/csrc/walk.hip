@@ -20,6 +20,7 @@
 // p = sum_{delta' < delta} (L - delta') + i.  Sample order (Algorithm 3 shuffles a
 // batch's pairs): sample s = b Bw P + p Bw + j is pair p of walk b Bw + j.
 #include <algorithm>
+#include <cmath>
 
 #include "handle.hpp"
 #include "scan.hpp"
@@ -410,6 +411,16 @@ lh_status walk_each_chunk(lh_handle *h, unsigned long long first, unsigned long 
                                                         unsigned long long)> &body)
 {
     WalkState &w = h->walk;
+    if (w.pool > 0) {
+        // Pair pool: the collected pairs are chunk 0's first R; every sample draws from them.
+        if (w.loaded != 0) {
+            w.loaded = -1;
+            hipError_t e = generate_chunk(h, 0);
+            if (e != hipSuccess) return hip_fail(h, e, "walk generation");
+            w.loaded = 0;
+        }
+        return count > 0 ? body(first, count, w.pairs, 0) : LH_OK;
+    }
     const unsigned long long cs = (unsigned long long)w.chunk_walks * (unsigned long long)w.P;
     const unsigned long long end = first + count;
     for (unsigned long long s = first; s < end;) {
@@ -485,10 +496,51 @@ lh_status lh_walk_detach(lh_handle *h)
     return LH_OK;
 }
 
+lh_status lh_walk_pool_size(uint64_t total_samples, uint64_t *pairs)
+{
+    if (!pairs || total_samples == 0) return LH_ERR_INVALID_ARG;
+    // least R >= 2 with R (R - 1) / 2 >= T: start from the binary64 root and correct it
+    unsigned long long R = (unsigned long long)std::ceil(0.5 * (1.0 + std::sqrt(1.0 + 8.0 * (double)total_samples)));
+    if (R < 2) R = 2;
+    auto tri = [](unsigned long long r) { return (unsigned __int128)r * (unsigned __int128)(r - 1) / 2; };
+    while (R > 2 && tri(R - 1) >= (unsigned __int128)total_samples) --R;
+    while (tri(R) < (unsigned __int128)total_samples) ++R;
+    *pairs = R;
+    return LH_OK;
+}
+
+lh_status lh_walk_pool(lh_handle *h, uint64_t pairs)
+{
+    if (!h) return LH_ERR_INVALID_ARG;
+    if (!h->walk.ready) return fail(h, LH_ERR_NOT_BUILT, "lh_walk_build first");
+    WalkState &w = h->walk;
+    const unsigned long long cap = (unsigned long long)w.chunk_walks * (unsigned long long)w.P;
+    if (pairs > cap) return fail(h, LH_ERR_OUT_OF_RANGE, "pool larger than the walk pair buffer");
+    w.pool = pairs;
+    if (pairs == 0) return LH_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != h->device) (void)hipSetDevice(h->device);
+    lh_status st = LH_OK;
+    if (w.loaded != 0) {
+        w.loaded = -1;
+        hipError_t e = generate_chunk(h, 0);
+        if (e != hipSuccess) {
+            w.pool = 0;
+            st = hip_fail(h, e, "walk generation");
+        } else {
+            w.loaded = 0;
+        }
+    }
+    if (prev >= 0 && prev != h->device) (void)hipSetDevice(prev);
+    return st;
+}
+
 lh_status lh_walk_pairs(lh_handle *h, uint64_t first, uint64_t count, int32_t *u, int32_t *v)
 {
     if (!h) return LH_ERR_INVALID_ARG;
     if (!h->walk.ready) return fail(h, LH_ERR_NOT_BUILT, "lh_walk_build first");
+    if (h->walk.pool > 0) return fail(h, LH_ERR_UNSUPPORTED, "a pair pool is on: lh_sample gives its pairs");
     if (count > 0 && (!u || !v)) return fail(h, LH_ERR_INVALID_ARG, "NULL output");
     if (first + count < first || count >= (1ull << 40)) return fail(h, LH_ERR_INVALID_ARG, "sample range out of range");
     int prev = -1;

@@ -108,6 +108,25 @@ def test_null_handles_rejected(L):
     assert L.lh_walk_pairs(None, 0, 1, None, None) == 1
     assert L.lh_walk_export(None, None, None, None, None) == 1
     assert L.lh_walk_detach(None) == 1
+    assert L.lh_walk_pool(None, 100) == 1
+
+
+def test_pool_size_is_the_oracles(L):
+    """The library's pool size for a run of T samples (host arithmetic from a binary64 root,
+    corrected in integers) equals the oracle's least R with R (R - 1) / 2 >= T."""
+    import oracle
+    out = ctypes.c_uint64()
+    Ts = list(range(1, 2000)) + [10**6, 2 * 10**8, 10**10, 2**40, 2**40 + 1, (1 << 40) * 3 + 7]
+    for T in Ts:
+        assert L.lh_walk_pool_size(T, ctypes.byref(out)) == 0
+        assert out.value == oracle.pool_size(T), T
+    # near the top of the range, where the binary64 root is inexact: check the definition
+    for T in (2**62, 2**63 + 12345, 2**64 - 1):
+        assert L.lh_walk_pool_size(T, ctypes.byref(out)) == 0
+        R = out.value
+        assert R * (R - 1) // 2 >= T > (R - 1) * (R - 2) // 2, T
+    assert L.lh_walk_pool_size(0, ctypes.byref(out)) == 1
+    assert L.lh_walk_pool_size(5, None) == 1
 
 
 @pytest.mark.parametrize("n,m,L_,W,Bw,ok", [
