@@ -126,10 +126,12 @@ def workload(name: str):
 WALK = dict(walk_length=100, window=2, walks_per_batch=1024)
 
 
-def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False, walks=None):
+def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False, walks=None, pool=False):
     """Time `steps` full passes (after `warmup`); return timings and the trainer.  With
     `walks`, every pass also builds the walk rows, and training takes its positive pairs
-    from random walks (their generation inside the timed training call)."""
+    from random walks (their generation inside the timed training call); with `pool` as
+    well, every pass collects a pair pool of the default size after the walk rows, and
+    training draws its pairs from it."""
     import torch
     from paper_2604_09419_amd import Trainer
     T = int(cfg["T"])
@@ -147,6 +149,8 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False
         tr.build_alias()
         if walks:
             tr.build_walks(**walks)
+        if pool:
+            tr.build_pool()
         tr.init_embeddings()
         tr.train_steps(0, T)
         tr.synchronize()
@@ -156,23 +160,26 @@ def run_gpu_leg(cfg, g, dtype, steps, warmup, seed, tune_cache, hot_shadow=False
         if i >= warmup:
             step_ms.append(dt)
             kern_ms.append(km)
-        log(f"[bench] {dtype}{' walks' if walks else ''} step {i} ({'warmup' if i < warmup else 'timed'}): "
+        kind = " pool" if pool else " walks" if walks else ""
+        log(f"[bench] {dtype}{kind} step {i} ({'warmup' if i < warmup else 'timed'}): "
             f"{dt:.1f} ms, train kernel {km:.1f} ms")
     tr.check()
     return tr, step_ms, kern_ms
 
 
-def walk_legs(args, cfg, g, hs, hd, neg, seed, T):
-    """C2 with positive pairs from random walks (WALK), binary32 and bfloat16 tables: step
-    and training-call rates (walk generation included), and held-out AUCs against the
-    oracle's binary64 SEQ run on the same walk pairs."""
+def walk_legs(args, cfg, g, hs, hd, neg, seed, T, pool=False):
+    """C2 with positive pairs from random walks (WALK), or with `pool` from a pair pool
+    collected from them (Sec. IV-C, Augmented-Pair), binary32 and bfloat16 tables: step and
+    training-call rates (walk generation included), and held-out AUCs against the
+    oracle's binary64 SEQ run on the same pairs."""
     import torch
-    out = {"pairs": f"random walks {WALK}"}
-    gold_path = os.path.join(GOLDEN, "c2_walk_oracle_auc.json")
+    out = {"pairs": (f"pair pool of the default size for T collected from random walks {WALK}" if pool
+                     else f"random walks {WALK}")}
+    gold_path = os.path.join(GOLDEN, "c2_pool_oracle_auc.json" if pool else "c2_walk_oracle_auc.json")
     gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
     for dtype in ("fp32", "bf16"):
         tr, steps_ms, kern_ms = run_gpu_leg(cfg, g, dtype, max(1, args.steps), 1, seed, args.tune_cache,
-                                            hot_shadow=args.hot_shadow, walks=WALK)
+                                            hot_shadow=args.hot_shadow, walks=WALK, pool=pool)
         leg = {"samples_per_s": T / (median(steps_ms) * 1e-3), "train_call_samples_per_s": T / (median(kern_ms) * 1e-3),
                "kernel_config": tr.kernel_config()}
         if not args.no_auc:
@@ -180,7 +187,7 @@ def walk_legs(args, cfg, g, hs, hd, neg, seed, T):
             if gold:
                 leg["auc_within_0.005_of_oracle"] = all(abs(v - gold["auc_" + k]) <= 0.005
                                                         for k, v in leg["auc"].items())
-            log(f"[bench] {dtype} walks AUC {leg['auc']}")
+            log(f"[bench] {dtype} {'pool' if pool else 'walks'} AUC {leg['auc']}")
         out[dtype] = leg
         tr.close()
         del tr
@@ -194,8 +201,8 @@ def walk_legs(args, cfg, g, hs, hd, neg, seed, T):
 def node_classification(args):
     """Sec. V-A's quality metric on the labelled stand-in graph (synth.labels.SBM): Micro-
     and Macro-F1 of a one-vs-rest logistic regression on 10 % of the labels, for vertex
-    embeddings trained on the GPU with arc-draw and with random-walk pairs, beside the
-    oracle's stored values."""
+    embeddings trained on the GPU with arc-draw pairs, random-walk pairs and pairs from a
+    pair pool (Sec. IV-C, Augmented-Pair), beside the oracle's stored values."""
     import torch
     from paper_2604_09419_amd import LH_TABLE_U, Trainer
     from synth.labels import node_classification_f1, sbm_workload
@@ -204,11 +211,13 @@ def node_classification(args):
                        f"{c['mean_degree']}, p_in {c['p_in']}; d={c['d']}, K={c['K']}, second order, "
                        f"{c['epochs']} epochs (T={c['T']})"}
     for dtype in ("fp32", "bf16"):
-        for pairs in ("arcs", "walks"):
+        for pairs in ("arcs", "walks", "pool"):
             tr = Trainer(g.n, g.src, g.dst, g.w, d=c["d"], K=c["K"], orders=c["orders"], dtype=dtype,
                          eta0=c["eta0"], seed=c["train_seed"], total_samples=c["T"])
-            if pairs == "walks":
+            if pairs in ("walks", "pool"):
                 tr.build_walks(**WALK)
+            if pairs == "pool":
+                tr.build_pool()
             tr.train_steps(0, c["T"])
             ms = tr.last_train_ms()
             micro, macro = node_classification_f1(tr.read(LH_TABLE_U).cpu().numpy(), labels, c["split_seed"])
@@ -217,10 +226,12 @@ def node_classification(args):
             del tr
             torch.cuda.empty_cache()
     gold_path = os.path.join(GOLDEN, "sbm_oracle_f1.json")
-    if os.path.exists(gold_path):
+    pool_path = os.path.join(GOLDEN, "sbm_pool_oracle_f1.json")
+    if os.path.exists(gold_path) and os.path.exists(pool_path):
         gold = json.load(open(gold_path))
+        gold.update({k: v for k, v in json.load(open(pool_path)).items() if k in ("pool", "pool_bf16")})
         out["oracle"] = {k: {"micro_f1": gold[k]["micro"], "macro_f1": gold[k]["macro"]}
-                         for k in ("arcs", "walks", "arcs_bf16", "walks_bf16") if k in gold}
+                         for k in ("arcs", "walks", "pool", "arcs_bf16", "walks_bf16", "pool_bf16") if k in gold}
         # the tolerance of the tests: max(0.01, 3 sd of the oracle's F1 over training seeds)
         def ok(v, ref):
             return all(abs(v[f"{a}_f1"] - ref[a]) <= max(0.01, 3.0 * ref[f"sd_{a}"]) for a in ("micro", "macro"))
@@ -552,7 +563,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 leg")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-c3-error", action="store_true", help="skip the C3 embedding-error leg")
-    ap.add_argument("--no-walks", action="store_true", help="skip the random-walk pair legs")
+    ap.add_argument("--no-walks", action="store_true", help="skip the random-walk and pair-pool legs")
     ap.add_argument("--no-f1", action="store_true", help="skip the node-classification leg")
     ap.add_argument("--walks", action="store_true",
                     help="C5 and C5U: positive pairs from random walks (the training call includes the walks)")
@@ -665,6 +676,7 @@ def main():
 
     if not args.no_walks:
         result["walks"] = walk_legs(args, cfg, g, hs, hd, neg, seed, T)
+        result["pool"] = walk_legs(args, cfg, g, hs, hd, neg, seed, T, pool=True)
     if not args.no_f1:
         result["node_classification"] = node_classification(args)
         log(f"[bench] node classification {result['node_classification']}")

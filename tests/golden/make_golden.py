@@ -8,6 +8,8 @@
     python tests/golden/make_golden.py c2_walk_auc   # C2 with random-walk pairs: about 40 minutes
     python tests/golden/make_golden.py mid_walk_auc  # the mid-size graph with random-walk pairs
     python tests/golden/make_golden.py sbm_f1        # labelled graph, node-classification F1: about 10 minutes
+    python tests/golden/make_golden.py c2_pool_auc   # C2 with pairs from a pair pool: about 40 minutes
+    python tests/golden/make_golden.py sbm_pool_f1   # labelled graph, pair-pool F1: about 5 minutes
 
 Each output JSON records the command, the workload and the oracle's binary64 result.
 """
@@ -29,18 +31,20 @@ from synth import CONFIGS, config_graph, mid_graph, small_batch  # noqa: E402
 WALK = dict(L=100, W=2, Bw=1024)
 
 
-def run_auc(name: str, orders: int, T: int, d: int, out: str, walks: bool = False):
+def run_auc(name: str, orders: int, T: int, d: int, out: str, walks: bool = False, pool: bool = False):
     cfg = CONFIGS[name]
     t0 = time.time()
     g, hs, hd, neg = config_graph(name, holdout=True)
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
     m = oracle.Model(tb, d=d, K=cfg["K"], orders=orders, T=T, seed=cfg["seed"],
                      eta0=cfg["eta0"])
-    wg = oracle.WalkGraph(tb, **WALK) if walks else None
+    wg = oracle.WalkGraph(tb, **WALK) if (walks or pool) else None
+    R = oracle.pool_size(T) if pool else 0
     res = {"workload": name, "n": g.n, "m_train": g.m, "held_out": int(hs.size), "d": d,
            "K": cfg["K"], "orders": orders, "T": T, "seed": cfg["seed"], "eta0": cfg["eta0"],
            "mode": "seq", "precision": "binary64",
-           "pairs": f"random walks {WALK}" if walks else "arc draws",
+           "pairs": (f"pair pool of {R} pairs collected from random walks {WALK}" if pool else
+                     f"random walks {WALK}" if walks else "arc draws"),
            "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
     def aucs(prefix):
         """Held-out AUC under each score: order 2 vertex.context (uc) and
@@ -57,7 +61,7 @@ def run_auc(name: str, orders: int, T: int, d: int, out: str, walks: bool = Fals
             res[f"{prefix}auc_{k}"] = oracle.auc(p, q)
 
     aucs("init_")
-    m.train(0, T, "seq", walks=wg)
+    m.train(0, T, "seq", walks=wg, pool=R)
     aucs("")
     res["oracle_seconds"] = round(time.time() - t0, 1)
     with open(os.path.join(HERE, out), "w") as f:
@@ -128,11 +132,12 @@ def _sbm_run(args):
     tb = oracle.Tables(g.n, g.src, g.dst, g.w)
     m = oracle.Model(tb, d=c["d"], K=c["K"], orders=c["orders"], T=c["T"], seed=train_seed, eta0=c["eta0"],
                      storage=storage)
-    m.train(0, c["T"], "seq", walks=oracle.WalkGraph(tb, **WALK) if pairs == "walks" else None)
+    wg = oracle.WalkGraph(tb, **WALK) if pairs in ("walks", "pool") else None
+    m.train(0, c["T"], "seq", walks=wg, pool=oracle.pool_size(c["T"]) if pairs == "pool" else 0)
     return pairs, storage, train_seed, node_classification_f1(m.U, labels, c["split_seed"])
 
 
-def run_sbm_f1(out: str):
+def run_sbm_f1(out: str, kinds=("arcs", "walks")):
     """Node-classification Micro/Macro-F1 (Sec. V-A) of the labelled workload's vertex
     embeddings U, trained by the oracle (SEQ) with arc-draw pairs and with random-walk
     pairs, with binary64 tables and with bfloat16 table storage (the precision
@@ -143,15 +148,17 @@ def run_sbm_f1(out: str):
     t0 = time.time()
     g, _, c = sbm_workload()
     seeds = [c["train_seed"], 70, 71]
-    jobs = [(p, st, s) for st in ("binary64", "bf16") for p in ("arcs", "walks") for s in seeds]
+    jobs = [(p, st, s) for st in ("binary64", "bf16") for p in kinds for s in seeds]
     with ProcessPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
         results = list(ex.map(_sbm_run, jobs))
     res = {"workload": "synth.labels.SBM", "config": SBM, "n": g.n, "m": g.m, "T": c["T"], "mode": "seq",
-           "precision": "binary64 arithmetic; binary64 tables (arcs, walks) or bfloat16 tables (arcs_bf16, "
+           "precision": "binary64 arithmetic; binary64 tables (arcs, walks, pool) or bfloat16 tables (arcs_bf16, "
                         "walks_bf16: nearest-rounded initial values, stochastically rounded writes)",
            "walk": WALK, "command": f"python tests/golden/make_golden.py {sys.argv[1]}"}
+    if "pool" in kinds:
+        res["pool_pairs"] = oracle.pool_size(c["T"])
     for storage in ("binary64", "bf16"):
-        for pairs in ("arcs", "walks"):
+        for pairs in kinds:
             rows = {s: f for p, st, s, f in results if p == pairs and st == storage}
             mi = [rows[s][0] for s in seeds]
             ma = [rows[s][1] for s in seeds]
@@ -185,5 +192,10 @@ if __name__ == "__main__":
         run_mid("mid_walk_oracle_auc.json", walks=True)
     elif which == "sbm_f1":
         run_sbm_f1("sbm_oracle_f1.json")
+    elif which == "c2_pool_auc":
+        run_auc("C2", orders=3, T=CONFIGS["C2"]["T"], d=CONFIGS["C2"]["d"], out="c2_pool_oracle_auc.json",
+                pool=True)
+    elif which == "sbm_pool_f1":
+        run_sbm_f1("sbm_pool_oracle_f1.json", kinds=("pool",))
     else:
         raise SystemExit(__doc__)

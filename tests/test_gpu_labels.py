@@ -7,7 +7,8 @@ The bar: the GPU's F1 (Hogwild, concurrent) within max(0.01, 3 sd) of the oracle
 with the same table storage, on the same pairs, the same training seed and the same
 label split, sd being the spread of the oracle's own F1 over three training seeds
 (stored with the reference: about 0.0015 with arc draws, 0.006 with walk pairs, whose
-pairs change with the seed as whole walks).  bfloat16 tables are held to the oracle run
+pairs change with the seed as whole walks).  Pairs from a pair pool (Sec. IV-C,
+Augmented-Pair) are held to the oracle's pool runs the same way.  bfloat16 tables are held to the oracle run
 with bfloat16 storage (every write stochastically rounded), the precision extension's
 reference; the stored binary64 value is printed beside it.
 """
@@ -28,18 +29,22 @@ def _bar(ref, key):
 
 
 
-@pytest.mark.parametrize("pairs", ["arcs", "walks"])
+@pytest.mark.parametrize("pairs", ["arcs", "walks", "pool"])
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
 def test_node_classification_f1_matches_oracle(dtype, pairs):
     import paper_2604_09419_amd as lh
     gold = json.load(open(os.path.join(GOLDEN, "sbm_oracle_f1.json")))
+    if pairs == "pool":
+        gold.update(json.load(open(os.path.join(GOLDEN, "sbm_pool_oracle_f1.json"))))
     g, labels, c = sbm_workload()
     assert (g.n, g.m, c["T"]) == (gold["n"], gold["m"], gold["T"])
     tr = trainer_for(g, d=c["d"], K=c["K"], orders=c["orders"], dtype=dtype, seed=c["train_seed"],
                      total_samples=c["T"], eta0=c["eta0"])
-    if pairs == "walks":
+    if pairs in ("walks", "pool"):
         w = gold["walk"]
         tr.build_walks(walk_length=w["L"], window=w["W"], walks_per_batch=w["Bw"])
+    if pairs == "pool":
+        assert tr.build_pool() == gold["pool_pairs"]
     tr.train_steps(0, c["T"])
     tr.check()
     micro, macro = node_classification_f1(tr.read(lh.LH_TABLE_U).cpu().numpy(), labels, c["split_seed"])

@@ -8,6 +8,9 @@ for C2's pool at its training size; SNAPSHOT training on pool pairs must agree w
 binary64 oracle within 1e-5 relative error per row; Hogwild training on pool pairs must
 match the oracle's held-out AUC within 0.005.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +21,9 @@ from gpu_util import dot_rows, max_row_rel_err, trainer_for
 
 pytestmark = pytest.mark.gpu
 WALK = dict(L=100, W=2, Bw=1024)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_09419_amd",
+                          "tune_cache.json")
 
 
 def _lh():
@@ -153,4 +159,36 @@ def test_pool_hogwild_c1_auc_matches_oracle(dtype):
            oracle.auc(dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg)))
     print(f"C1 pool {dtype}: uc {got[0]:.4f} (oracle {ref[0]:.4f}) uu {got[1]:.4f} (oracle {ref[1]:.4f})", flush=True)
     assert abs(got[0] - ref[0]) <= 0.005 and abs(got[1] - ref[1]) <= 0.005
+    tr.close()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "c2_pool_oracle_auc.json")),
+                    reason="stored reference not written yet (make_golden.py c2_pool_auc)")
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_pool_hogwild_c2_auc_matches_oracle(dtype):
+    """C2 (orders 1+2, T = 2e8) on its pool of 20,001 pairs, in the tile shape the bench
+    times: every held-out AUC within 0.005 of the oracle's SEQ binary64 run."""
+    from synth import CONFIGS
+    lh = _lh()
+    gold = json.load(open(os.path.join(GOLDEN, "c2_pool_oracle_auc.json")))
+    cfg = CONFIGS["C2"]
+    g, hs, hd, neg = config_graph("C2", holdout=True)
+    assert (g.n, g.m, hs.size) == (gold["n"], gold["m_train"], gold["held_out"])
+    tr = trainer_for(g, d=cfg["d"], K=cfg["K"], orders=3, dtype=dtype, seed=cfg["seed"], total_samples=cfg["T"])
+    tr.tune(probe=20_000_000, cache_path=TUNE_CACHE)
+    tr.build_walks(walk_length=WALK["L"], window=WALK["W"], walks_per_batch=WALK["Bw"])
+    tr.build_pool()
+    tr.train_steps(0, cfg["T"])
+    tr.check()
+    U = tr.read(lh.LH_TABLE_U).cpu().numpy()
+    C = tr.read(lh.LH_TABLE_C).cpu().numpy()
+    U1 = tr.read(lh.LH_TABLE_U1).cpu().numpy()
+    uu = (dot_rows(U, U, hs, hd), dot_rows(U, U, hs, neg))
+    o1 = (dot_rows(U1, U1, hs, hd), dot_rows(U1, U1, hs, neg))
+    got = {"uc": oracle.auc(dot_rows(U, C, hs, hd), dot_rows(U, C, hs, neg)), "uu": oracle.auc(*uu),
+           "o1": oracle.auc(*o1), "concat": oracle.auc(uu[0] + o1[0], uu[1] + o1[1])}
+    for k, v in got.items():
+        print(f"C2 pool {dtype} {k}: {v:.4f} (oracle {gold['auc_' + k]:.4f})", flush=True)
+    for k, v in got.items():
+        assert abs(v - gold["auc_" + k]) <= 0.005, k
     tr.close()
