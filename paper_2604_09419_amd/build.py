@@ -29,6 +29,13 @@ COMMON = [
 ]
 # The alias construction must round every binary64 operation on its own.
 PER_FILE = {"alias.hip": ["-ffp-contract=off"], "walk.hip": ["-ffp-contract=off"]}
+# Training units: a branch on a wave-uniform condition (a row's store or atomic) stays one
+# if/else instead of two guarded blocks, so the compiler knows that exactly one write
+# follows each row and its waits on vmcnt cover only the loads they need.
+UNIFORM_BRANCHES = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+for _name in ("sgd_f32_o1.hip", "sgd_f32_o2.hip", "sgd_f32_o3.hip", "sgd_bf16_o1.hip", "sgd_bf16_o2.hip",
+              "sgd_bf16_o3.hip", "batch.hip"):
+    PER_FILE[_name] = UNIFORM_BRANCHES
 
 
 def _headers_mtime() -> float:
