@@ -363,23 +363,27 @@ def test_bf16_shape_follows_the_hot_share():
     assert hub.kernel_config() == {"lanes_per_sample": 64, "units_per_lane": 1, "blocks_per_cu": 16}
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
-def test_hot_and_cold_writes_agree_bitwise_without_concurrency(dtype):
+@pytest.mark.parametrize("dtype,d,shape", [("fp32", 64, None), ("bf16", 64, None), ("fp32", 128, (64, 2, 4))])
+def test_hot_and_cold_writes_agree_bitwise_without_concurrency(dtype, d, shape):
     """One sample per launch, so no write overlaps another: a run where every row takes the
     atomic (hot) path must leave the tables bit-identical to a run where every row takes the
     store (cold) path.  binary32: old + inc rounded once either way.  bfloat16: the packed
     atomic adds SR(old + inc) - old, drawn with the cold store's random bits; that
     difference is exact (Sterbenz) while old and SR(old + inc) are within a factor of two,
     so the tables start with every |value| in [2^-6, 2^-5) and the step stays far below
-    that (the general case is bounded in tests/test_bf16_rounding.py)."""
+    that (the general case is bounded in tests/test_bf16_rounding.py).  The binary32 case at
+    the C2 tile shape (one sample per wavefront) writes cold rows with the streaming buffer
+    stores."""
     lh = _lh()
     g = rmat_graph(12, 3000, 30_000, seed=11)
     rng = np.random.default_rng(13)
-    start = [(rng.choice([-1.0, 1.0], (g.n, 64)) * (1.0 + rng.integers(0, 128, (g.n, 64)) / 128.0) * 2.0 ** -6)
+    start = [(rng.choice([-1.0, 1.0], (g.n, d)) * (1.0 + rng.integers(0, 128, (g.n, d)) / 128.0) * 2.0 ** -6)
              .astype(np.float32) for _ in range(3)]
     out = []
     for hot_rate in (0.0, 1e31):  # <= 0: every row hot; >= 1e30: none
-        tr = trainer_for(g, d=64, K=5, orders=3, dtype=dtype, seed=12, total_samples=10_000, hot_rate=hot_rate)
+        tr = trainer_for(g, d=d, K=5, orders=3, dtype=dtype, seed=12, total_samples=10_000, hot_rate=hot_rate)
+        if shape is not None:
+            tr.set_kernel_config(*shape)
         for t in (lh.LH_TABLE_U, lh.LH_TABLE_C, lh.LH_TABLE_U1):
             tr.write(t, start[t])
         for s in range(300):
