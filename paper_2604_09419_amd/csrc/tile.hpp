@@ -241,15 +241,18 @@ __device__ __forceinline__ void store_coherent(uint32_t *p, uint32_t v)
 // A cold binary32 row written by a whole wavefront (64 lanes per sample, so the row address
 // is uniform): buffer stores through a descriptor of the row, with the system-scope bits and
 // the non-temporal hint (cache policy sc0 | nt | sc1).  Measured on the C2 workload the
-// training launch takes 539.9 instead of 568.8 ms; the same stores slow bfloat16 rows down
-// (C3: 319.4 against 303.0 ms), so those keep the global store.  The descriptor's range is
-// the row, so no store can leave it.
+// training launch takes 539.9 instead of 568.8 ms at 2 workgroups per CU, and 520 ms at the
+// 4 the tuner then picks; the same stores slow bfloat16 rows down (C3: 319.4 against
+// 303.0 ms), so those keep the global store.  The descriptor's range is the row, so no store
+// can leave it; its last word (0x00020000) is the 32-bit data format that untyped buffer
+// accesses use on gfx9-family devices.
 constexpr int kCpolSysNT = 1 | 2 | 16;
+constexpr int kRawBufferWord3 = 0x00020000;
 
 template <int LPS, int UPL, bool FULL>
 __device__ __forceinline__ void store_row_stream(uint32_t *row, int nunits, int gl, const uint32_t (&word)[UPL])
 {
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, (short)0, nunits * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, (short)0, nunits * 4, kRawBufferWord3);
 #pragma unroll
     for (int k = 0; k < UPL; ++k) {
         const int un = k * LPS + gl;
