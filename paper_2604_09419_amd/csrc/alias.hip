@@ -98,12 +98,28 @@ lh_status validate_graph(lh_handle *h)
 // ---------------------------------------------------------------------------
 // Weights of the two tables, binary64.
 // ---------------------------------------------------------------------------
-__global__ void k_degrees(const int32_t *src, const int32_t *dst, long long m, int32_t *deg, int32_t *indeg)
+// Out-degrees add one per run of equal consecutive sources inside a wavefront (arc lists
+// are often grouped by source), in-degrees one per arc.  The valid lanes of a wavefront are a
+// prefix of it (a = block * 256 + thread), so a run ends at the next run head or at the
+// first invalid lane.
+__global__ void __launch_bounds__(256) k_degrees(const int32_t *src, const int32_t *dst, long long m, int32_t *deg,
+                                                 int32_t *indeg)
 {
-    long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m) return;
-    atomicAdd(&deg[src[a]], 1);
-    atomicAdd(&indeg[dst[a]], 1);
+    const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = a < m;
+    const int s = ok ? src[a] : -1;
+    if (ok) atomicAdd(&indeg[dst[a]], 1);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int prev = __shfl_up(s, 1);
+    const bool head = ok && (lane == 0 || prev != s);
+    const unsigned long long heads = __ballot(head);
+    const int nvalid = __popcll(__ballot(ok));
+    if (head) {
+        const unsigned long long above = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+        int next = above ? __ffsll((long long)above) - 1 : 64;
+        if (next > nvalid) next = nvalid;
+        atomicAdd(&deg[s], next - lane);
+    }
 }
 
 // Heat of node r (see common.hpp): floor(-log2 p_r), p_r = (out + in) / m + K nu_r / W_nu.

@@ -239,6 +239,29 @@ __global__ void k_init(TT *X, int t, long long rows, int d, unsigned long long s
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n4 = (d + 3) / 4;
     if (i >= rows * n4) return;
+    // d a power of two (d >= 8): the row and group come from shifts, and the value is formed
+    // in binary32. The integer (x >> 40) - 2^23 has at most 24 significant bits and 2^-24 / d
+    // is a power of two, so both the binary64 expression and this one are exact and equal
+    // bit for bit; the four values of a group are one 16-byte (8-byte) store.
+    if ((d & (d - 1)) == 0 && d >= 8 && ((uintptr_t)X % (4 * sizeof(TT))) == 0) {
+        const int sh = __builtin_ctz((unsigned)n4);
+        const long long r = i >> sh;
+        const int c4 = (int)(i & (long long)(n4 - 1));
+        const u64x4 x = philox4x64_10(seed, key1, (unsigned long long)r, (unsigned long long)c4, (unsigned long long)t, 0ull);
+        const float scale = 0x1p-24f / (float)d;
+        float f[4];
+        const unsigned long long w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = (float)((int)(w[k] >> 40) - 8388608) * scale;
+        if constexpr (sizeof(TT) == 4) {
+            *reinterpret_cast<float4 *>(X + r * d + c4 * 4) = make_float4(f[0], f[1], f[2], f[3]);
+        } else {
+            const uint32_t lo = f32_to_bf16_rne(f[0]) | (f32_to_bf16_rne(f[1]) << 16);
+            const uint32_t hi = f32_to_bf16_rne(f[2]) | (f32_to_bf16_rne(f[3]) << 16);
+            *reinterpret_cast<uint2 *>(X + r * d + c4 * 4) = make_uint2(lo, hi);
+        }
+        return;
+    }
     long long r = i / n4;
     int c4 = (int)(i % n4);
     u64x4 x = philox4x64_10(seed, key1, (unsigned long long)r, (unsigned long long)c4, (unsigned long long)t, 0ull);
