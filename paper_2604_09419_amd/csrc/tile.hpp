@@ -15,7 +15,8 @@
 //            per-row contributions (SNAPSHOT, Eq. (4)).
 //
 // HOGWILD write-back: a cold row is stored (row as loaded plus the sample's increment;
-// no locks) with a system-scope store, and every table row is loaded with system scope,
+// no locks) with a system-scope store (binary32 rows of a one-sample wavefront: a
+// system-scope non-temporal buffer store), and every table row is loaded with system scope,
 // so the eight XCDs' L2 caches never hold diverging copies.  A hot row -- one that an
 // in-flight sample is likely to share, a hub -- is updated with atomic increments so that
 // concurrent updates are not lost: binary32 atomics for binary32 tables; for bfloat16
