@@ -83,12 +83,27 @@ __device__ __forceinline__ SlotDraw draw_slot(const GraphDev &g, unsigned long l
     return SlotDraw{draw_column(x.x, N), x.y, x.z};
 }
 
-// The 32-byte edge record of a column as two 16-byte words (one sector).
+// The 32-byte edge record of a column as two 16-byte words (one sector).  NT: loaded with
+// the non-temporal hint.  Columns are uniform over the arcs, so an edge record is almost
+// never read twice while cached; with bfloat16 tables the hint leaves the caches to rows
+// and negative records (C3: 293.8 against 302.4-304.4 ms; C5: 1,236-1,260 against
+// 1,228-1,348 ms over three alternating runs each).  With binary32 tables it measured
+// 0.2 % slower, so those keep the plain load.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool NT = false>
 __device__ __forceinline__ void load_edge_rec(const EdgeRec *erec, long long col, uint4 &r0, uint4 &r1)
 {
-    const uint4 *er = reinterpret_cast<const uint4 *>(erec + col);
-    r0 = er[0];
-    r1 = er[1];
+    if constexpr (NT) {
+        const u32x4_t *er = reinterpret_cast<const u32x4_t *>(erec + col);
+        const u32x4_t a = __builtin_nontemporal_load(er), b = __builtin_nontemporal_load(er + 1);
+        r0 = make_uint4(a.x, a.y, a.z, a.w);
+        r1 = make_uint4(b.x, b.y, b.z, b.w);
+    } else {
+        const uint4 *er = reinterpret_cast<const uint4 *>(erec + col);
+        r0 = er[0];
+        r1 = er[1];
+    }
 }
 
 // Columns of slot 0's draw: the edge table's arcs, or the pair pool's collected pairs.
@@ -103,11 +118,12 @@ __device__ __forceinline__ long long slot0_columns(const GraphDev &g)
 // the heats of u and v in the record's heat word.  With a pair pool (Sec. IV-C,
 // Augmented-Pair) the pair is the first vertex of collected pair col (the first column
 // draw) and the second vertex of collected pair floor(x1 R / 2^64) (the second word).
+template <bool NT = false>
 __device__ __forceinline__ void load_pair_rec(const GraphDev &g, unsigned long long s, long long col,
                                               unsigned long long x1, uint4 &r0, uint4 &r1)
 {
     if (g.pairs == nullptr) {
-        load_edge_rec(g.erec, col, r0, r1);
+        load_edge_rec<NT>(g.erec, col, r0, r1);
         return;
     }
     int2 p;
@@ -596,7 +612,7 @@ __device__ __forceinline__ void sgd_tile(const GraphDev &g, unsigned long long t
             // (which would hold 1 + K blocks of state in registers).
             const SlotDraw de = draw_slot(g, s, 0, slot0_columns(g));
             uint4 r0, r1;
-            load_pair_rec(g, s, de.col, de.x1, r0, r1);
+            load_pair_rec<sizeof(TT) == 2>(g, s, de.col, de.x1, r0, r1);
             my_sr = (uint32_t)de.x2;
             __builtin_amdgcn_sched_barrier(0);
             SlotDraw dn[KMAX];
