@@ -86,9 +86,8 @@ __device__ __forceinline__ SlotDraw draw_slot(const GraphDev &g, unsigned long l
 // The 32-byte edge record of a column as two 16-byte words (one sector).  NT: loaded with
 // the non-temporal hint.  Columns are uniform over the arcs, so an edge record is almost
 // never read twice while cached; with bfloat16 tables the hint leaves the caches to rows
-// and negative records (C3: 293.8 against 302.4-304.4 ms; C5: 1,236-1,260 against
-// 1,228-1,348 ms over three alternating runs each).  With binary32 tables it measured
-// 0.2 % slower, so those keep the plain load.
+// and negative records (C3: 293.8 against 302.4-304.4 ms).  With binary32 tables it
+// measured 0.2 % slower, so those keep the plain load.
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 template <bool NT = false>
